@@ -1,0 +1,227 @@
+/*
+ * afmm.h -- C ABI of the MI355X (gfx950) AFMM library, libafmm.so.
+ *
+ * AFMM (Singh, Chakraborty, Mallick, arXiv 1308.2400, Section 2) forms the
+ * product Z = X . Y of two dense n x n matrices, one of which holds
+ * non-negative integers, without a single multiplication: every product
+ * term X[i,k] * Y[k,j] is made by adding the real entry into Z[i,j] as many
+ * times as the integer entry says.
+ *   Case A (Section 2, Case-A loop): X real (binary32), Y integer (int32).
+ *       For each non-zero X[i,k] and each j, X[i,k] is added into Z[i,j]
+ *       Y[k,j] times.
+ *   Case B (Section 2, Case-B loop): X integer, Y real.  For each j with a
+ *       non-zero Y[k,j], Y[k,j] is added into Z[i,j] X[i,k] times.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are dense, row-major, n x n, contiguous (element (r, c) at
+ *    r * n + c), 4-byte aligned, in device memory owned by the caller.  The
+ *    library keeps no pointer after a call returns (plans excepted: they keep
+ *    theirs until destroyed).
+ *  - Z is fully overwritten: it starts from zero (Section 2: "Z ... initialized
+ *    with all zeroes"); there is no accumulate mode.  Z may not overlap X or Y.
+ *  - Work is queued on `stream` (0 = the null stream) and the call returns
+ *    without waiting, except afmm_validate.  Argument errors are detected on
+ *    the host before anything is queued; a failed launch returns
+ *    AFMM_ERR_HIP and afmm_last_hip_error() gives the HIP error code.
+ *  - Integer entries are repetition counts (Section 2.1: the Rep-factor is an
+ *    integer count).  An entry <= 0 performs no additions (the empty sum).
+ *    Entries are not checked by the multiply calls; afmm_validate and
+ *    afmm_count_adds report negative and out-of-range entries.
+ *  - Non-finite reals are outside the contract (they propagate as IEEE says).
+ *  - Calls are thread-safe; calls on different streams may overlap.
+ *
+ * Precision modes
+ *  - AFMM_MODE_STRICT: the method itself.  Every addition is a binary32
+ *    round-to-nearest-even addition performed in the paper's order (k
+ *    ascending, then the Rep-factor repetitions, straight into Z[i,j]), so
+ *    the result is bit-identical to a sequential CPU run of the Case-A or
+ *    Case-B loop in binary32 with denormals kept.
+ *  - AFMM_MODE_SPLIT_BF16X3: the same product on the matrix cores: the real
+ *    factor is split into three bfloat16 terms (hi + mid + lo == x exactly
+ *    for 2^-100 <= |x| < 2^127), the integer factor is held exactly in
+ *    bfloat16 (requires 0 <= entry <= 256), and the terms are contracted with
+ *    MFMA into binary32 accumulators.  Not bit-identical to STRICT; relative
+ *    Frobenius error against the exact product stays near 1e-7 on the
+ *    reference workloads.  Uses multiplications (on the matrix cores).
+ */
+#ifndef AFMM_H
+#define AFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { AFMM_CASE_A = 0, AFMM_CASE_B = 1 } afmm_case;
+
+typedef enum { AFMM_MODE_STRICT = 0, AFMM_MODE_SPLIT_BF16X3 = 1 } afmm_mode;
+
+typedef enum {
+    AFMM_OK = 0,
+    AFMM_ERR_INVALID_ARG = 1,    /* null pointer, n < 1, n > AFMM_MAX_N, bad enum      */
+    AFMM_ERR_ALIAS = 2,          /* Z overlaps X or Y                                  */
+    AFMM_ERR_NEGATIVE_INT = 3,   /* afmm_validate: an integer entry is negative        */
+    AFMM_ERR_INT_RANGE = 4,      /* afmm_validate: entry > 256 in split mode           */
+    AFMM_ERR_COUNT_OVERFLOW = 5, /* afmm_validate: the add count exceeds 2^64 - 1      */
+    AFMM_ERR_NO_DEVICE = 6,      /* no usable gfx950 device                            */
+    AFMM_ERR_HIP = 7,            /* a HIP call failed; see afmm_last_hip_error()       */
+    AFMM_ERR_UNSUPPORTED = 8,    /* valid request this build does not implement        */
+    AFMM_ERR_WORKSPACE = 9       /* workspace given but smaller than required          */
+} afmm_status;
+
+/* Largest supported n (element offsets stay below 2^31 per row stride). */
+#define AFMM_MAX_N 65536
+
+/* Flag bits written by afmm_count_adds into *d_flags. */
+#define AFMM_FLAG_NEGATIVE 1u /* an integer entry is < 0                      */
+#define AFMM_FLAG_ABOVE255 2u /* an integer entry is > 255                    */
+#define AFMM_FLAG_ABOVE256 4u /* an integer entry is > 256 (split mode: bad)  */
+#define AFMM_FLAG_OVERFLOW 8u /* the add count saturated at 2^64 - 1          */
+
+/*
+ * Bytes of device scratch a multiply of this case, size and mode needs.
+ * Pass at least that much as `workspace` to the multiply calls, or pass
+ * workspace = NULL to let the library take it from the stream-ordered HIP
+ * allocator (hipMallocAsync / hipFreeAsync on `stream`).
+ */
+size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode);
+
+/*
+ * Case A product (Section 2, Case-A loop).  X: n x n binary32, Y: n x n
+ * int32 (repetition counts), Z: n x n binary32 output.  See the mode notes
+ * above.  workspace / workspace_bytes: caller scratch or NULL / 0.
+ */
+afmm_status afmm_multiply_caseA(int64_t n, const float *X, const int32_t *Y, float *Z,
+                                afmm_mode mode, void *workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+/* Case B product (Section 2, Case-B loop).  X: int32 counts, Y: binary32. */
+afmm_status afmm_multiply_caseB(int64_t n, const int32_t *X, const float *Y, float *Z,
+                                afmm_mode mode, void *workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+/*
+ * Number of additions the method performs on (X, Y) (Section 2.2, counted
+ * exactly rather than estimated as mu' d1 d2 n^3):
+ *   case A: sum over (i,k) with X[i,k] != 0 and over j of max(Y[k,j], 0)
+ *   case B: sum over (i,k) and over j with Y[k,j] != 0 of max(X[i,k], 0)
+ * Writes into device memory: *d_total (uint64, saturated at 2^64-1),
+ * d_row_counts[i] = additions of row i of Z (nullable), *d_flags = the
+ * AFMM_FLAG_* bits found (nullable).  Needs n * 8 bytes of workspace (or
+ * NULL, see afmm_workspace_size).  Asynchronous.
+ */
+afmm_status afmm_count_adds(afmm_case c, int64_t n, const void *X, const void *Y,
+                            uint64_t *d_total, uint64_t *d_row_counts, uint32_t *d_flags,
+                            void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Synchronous data check: runs the counting pass on `stream`, waits for it,
+ * and returns AFMM_ERR_NEGATIVE_INT, AFMM_ERR_INT_RANGE (split mode, an
+ * entry > 256), AFMM_ERR_COUNT_OVERFLOW or AFMM_OK.
+ */
+afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, afmm_mode mode,
+                          hipStream_t stream);
+
+/*
+ * Kernel configuration of the strict path (the autotuner's knobs).
+ *   mapping: 0 = rep-uniform (each wave walks R rows of the integer factor
+ *            with the count in a scalar register; lanes over the real
+ *            factor's columns; case A runs on the transposed problem),
+ *            1 = base-uniform (case A only: each wave walks R rows of X with
+ *            the base in a scalar register; lanes over Y's columns with a
+ *            per-lane count).
+ *   rows_per_wave R, cols_per_lane C, waves per workgroup W: one of the
+ *   compiled combinations (afmm_config_supported tells which).
+ */
+typedef struct {
+    int32_t mapping;
+    int32_t rows_per_wave;
+    int32_t cols_per_lane;
+    int32_t waves;
+} afmm_config;
+
+/* 1 when `cfg` names a compiled kernel for case c, else 0. */
+int afmm_config_supported(afmm_case c, const afmm_config *cfg);
+
+/* The configuration the library picks for a strict product of this case and
+ * size (tuning table, else built-in rule). */
+afmm_config afmm_default_config(afmm_case c, int64_t n);
+
+/* Strict product with an explicit configuration (for the autotuner). */
+afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void *X, const void *Y,
+                                        float *Z, const afmm_config *cfg, void *workspace,
+                                        size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Tuning table: `count` entries, entry t applying to products of case
+ * cases[t] with n in [n_lo[t], n_hi[t]].  Replaces the previous table; a
+ * later entry wins over an earlier one.  Entries naming an unsupported
+ * configuration are rejected (AFMM_ERR_INVALID_ARG, table unchanged).
+ */
+afmm_status afmm_set_tuning(int32_t count, const int32_t *cases, const int64_t *n_lo,
+                            const int64_t *n_hi, const afmm_config *cfgs);
+
+/* ---------------------------------------------------------------------------
+ * Batched products: many independent AFMM products of uneven size, density
+ * and integer range in one persistent launch.  Work is cut into tiles and
+ * handed out largest-first by each tile's addition count (the method's own
+ * cost, Section 2.2), measured on the device from the data.
+ */
+typedef struct {
+    int32_t case_id; /* AFMM_CASE_A or AFMM_CASE_B                             */
+    int32_t n;       /* 1 .. AFMM_MAX_BATCH_N                                  */
+    const void *X;   /* case A: const float*, case B: const int32_t*           */
+    const void *Y;   /* case A: const int32_t*, case B: const float*           */
+    float *Z;        /* output, must not overlap any X or Y of the batch       */
+} afmm_problem;
+
+#define AFMM_MAX_BATCH_N 8192
+
+typedef struct afmm_plan afmm_plan;
+
+/*
+ * Build a plan for `count` problems (host array, copied).  Strict mode only
+ * (split mode returns AFMM_ERR_UNSUPPORTED).  Allocates the plan's device
+ * tables and scratch on the current device.  The plan records the pointers;
+ * the data they point to may change between launches.
+ */
+afmm_status afmm_plan_create(const afmm_problem *problems, int32_t count, afmm_mode mode,
+                             afmm_plan **out);
+
+/*
+ * Run the plan on `stream`: prepare operands, compute per-tile addition
+ * counts, order the tiles largest-first, and run the persistent kernel.  The
+ * first launch on a stream captures these steps into a HIP graph; later
+ * launches replay it.  Launches of one plan must not overlap.
+ */
+afmm_status afmm_plan_launch(afmm_plan *plan, hipStream_t stream);
+
+/* Queue on `stream` a copy of the per-problem addition counts computed by
+ * the plan's last launch into d_out (device, uint64[count]). */
+afmm_status afmm_plan_problem_adds(const afmm_plan *plan, uint64_t *d_out, hipStream_t stream);
+
+/* Release the plan (synchronises the device first). */
+afmm_status afmm_plan_destroy(afmm_plan *plan);
+
+/* One-shot convenience: create, launch on `stream`, wait, destroy. */
+afmm_status afmm_multiply_batched(const afmm_problem *problems, int32_t count, afmm_mode mode,
+                                  hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+const char *afmm_status_string(afmm_status s);
+
+/* HIP error code of the last AFMM_ERR_HIP on this thread (0 if none). */
+int afmm_last_hip_error(void);
+
+/* Library version, "major.minor.patch". */
+const char *afmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,265 @@
+"""Python binding of libafmm, the gfx950 AFMM library (C ABI: include/afmm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libafmm.so.  PyTorch supplies device memory and the current
+stream.  Importing fails loudly when the library is not built.
+
+Two layers:
+  * the C entry points under their own names (``afmm_multiply_caseA`` ...),
+    taking integer device pointers, sizes and a stream handle;
+  * tensor helpers: ``multiply``, ``count_adds``, ``validate``, ``Plan``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafmm.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+CASE_A, CASE_B = 0, 1
+MODE_STRICT, MODE_SPLIT_BF16X3 = 0, 1
+FLAG_NEGATIVE, FLAG_ABOVE255, FLAG_ABOVE256, FLAG_OVERFLOW = 1, 2, 4, 8
+STATUS = {0: "AFMM_OK", 1: "AFMM_ERR_INVALID_ARG", 2: "AFMM_ERR_ALIAS",
+          3: "AFMM_ERR_NEGATIVE_INT", 4: "AFMM_ERR_INT_RANGE", 5: "AFMM_ERR_COUNT_OVERFLOW",
+          6: "AFMM_ERR_NO_DEVICE", 7: "AFMM_ERR_HIP", 8: "AFMM_ERR_UNSUPPORTED",
+          9: "AFMM_ERR_WORKSPACE"}
+
+
+class afmm_config(ctypes.Structure):
+    _fields_ = [("mapping", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
+                ("cols_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.mapping, self.rows_per_wave, self.cols_per_lane, self.waves)
+
+
+class afmm_problem(ctypes.Structure):
+    _fields_ = [("case_id", ctypes.c_int32), ("n", ctypes.c_int32), ("X", ctypes.c_void_p),
+                ("Y", ctypes.c_void_p), ("Z", ctypes.c_void_p)]
+
+
+_vp, _i64, _i32, _sz, _ci = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t,
+                             ctypes.c_int)
+_SIGS = {
+    "afmm_workspace_size": ([_ci, _i64, _ci], _sz),
+    "afmm_multiply_caseA": ([_i64, _vp, _vp, _vp, _ci, _vp, _sz, _vp], _ci),
+    "afmm_multiply_caseB": ([_i64, _vp, _vp, _vp, _ci, _vp, _sz, _vp], _ci),
+    "afmm_count_adds": ([_ci, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _ci),
+    "afmm_validate": ([_ci, _i64, _vp, _vp, _ci, _vp], _ci),
+    "afmm_config_supported": ([_ci, ctypes.POINTER(afmm_config)], _ci),
+    "afmm_default_config": ([_ci, _i64], afmm_config),
+    "afmm_multiply_strict_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config), _vp,
+                                     _sz, _vp], _ci),
+    "afmm_set_tuning": ([_i32, _vp, _vp, _vp, _vp], _ci),
+    "afmm_plan_create": ([ctypes.POINTER(afmm_problem), _i32, _ci, ctypes.POINTER(_vp)], _ci),
+    "afmm_plan_launch": ([_vp, _vp], _ci),
+    "afmm_plan_problem_adds": ([_vp, _vp, _vp], _ci),
+    "afmm_plan_destroy": ([_vp], _ci),
+    "afmm_multiply_batched": ([ctypes.POINTER(afmm_problem), _i32, _ci, _vp], _ci),
+    "afmm_status_string": ([_ci], ctypes.c_char_p),
+    "afmm_last_hip_error": ([], _ci),
+    "afmm_version": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()[_name] = _f  # the C entry points under their own names
+
+
+class AfmmError(RuntimeError):
+    def __init__(self, where, status):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} "
+                         f"({_lib.afmm_status_string(status).decode()}; "
+                         f"hip error {_lib.afmm_last_hip_error()})")
+
+
+def _check(where, st):
+    if st != 0:
+        raise AfmmError(where, st)
+
+
+def _case_id(case):
+    if case in ("A", "a", CASE_A):
+        return CASE_A
+    if case in ("B", "b", CASE_B):
+        return CASE_B
+    raise ValueError(f"case must be 'A' or 'B', not {case!r}")
+
+
+def _mode_id(mode):
+    if mode in ("strict", MODE_STRICT):
+        return MODE_STRICT
+    if mode in ("split", "split_bf16x3", MODE_SPLIT_BF16X3):
+        return MODE_SPLIT_BF16X3
+    raise ValueError(f"mode must be 'strict' or 'split_bf16x3', not {mode!r}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _operands(case, X, Y):
+    torch = _torch()
+    c = _case_id(case)
+    xdt, ydt = (torch.float32, torch.int32) if c == CASE_A else (torch.int32, torch.float32)
+    for name, t, dt in (("X", X, xdt), ("Y", Y, ydt)):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dtype != dt:
+            raise TypeError(f"case {'AB'[c]}: {name} must be {dt}, got {t.dtype}")
+        if t.dim() != 2 or t.shape[0] != t.shape[1] or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous square matrix")
+    if X.shape != Y.shape or X.device != Y.device:
+        raise ValueError("X and Y must have the same shape and device")
+    return c, X.shape[0]
+
+
+def workspace_size(case, n, mode="strict") -> int:
+    return int(_lib.afmm_workspace_size(_case_id(case), n, _mode_id(mode)))
+
+
+def multiply(case, X, Y, mode="strict", out=None, workspace=None, config=None):
+    """Z = X . Y by AFMM (case 'A': X float32, Y int32; case 'B': X int32, Y float32)."""
+    torch = _torch()
+    c, n = _operands(case, X, Y)
+    m = _mode_id(mode)
+    Z = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=X.device)
+    if Z.dtype != torch.float32 or tuple(Z.shape) != (n, n) or not Z.is_contiguous():
+        raise ValueError("out must be a contiguous float32 n x n tensor")
+    if workspace is None:
+        need = workspace_size(c, n, m)
+        if config is not None:
+            need = max(need, workspace_size(c, n, MODE_STRICT))
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    ws, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    if config is not None:
+        if m != MODE_STRICT:
+            raise ValueError("an explicit config applies to the strict mode only")
+        cfg = config if isinstance(config, afmm_config) else afmm_config(*config)
+        st = _lib.afmm_multiply_strict_config(c, n, X.data_ptr(), Y.data_ptr(), Z.data_ptr(),
+                                              ctypes.byref(cfg), ws, wsb, _stream())
+    else:
+        fn = _lib.afmm_multiply_caseA if c == CASE_A else _lib.afmm_multiply_caseB
+        st = fn(n, X.data_ptr(), Y.data_ptr(), Z.data_ptr(), m, ws, wsb, _stream())
+    _check("multiply", st)
+    return Z
+
+
+def count_adds_async(case, X, Y, rows=False):
+    """Queue the exact addition count; returns device tensors (total[1], flags[1], rows|None)."""
+    torch = _torch()
+    c, n = _operands(case, X, Y)
+    total = torch.empty(1, dtype=torch.uint64, device=X.device)
+    flags = torch.empty(1, dtype=torch.int32, device=X.device)
+    rc = torch.empty(n, dtype=torch.uint64, device=X.device) if rows else None
+    ws = torch.empty(workspace_size(c, n), dtype=torch.uint8, device=X.device)
+    st = _lib.afmm_count_adds(c, n, X.data_ptr(), Y.data_ptr(), total.data_ptr(),
+                              rc.data_ptr() if rc is not None else None, flags.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream())
+    _check("count_adds", st)
+    return total, flags, rc
+
+
+def count_adds(case, X, Y, rows=False, with_flags=False):
+    """Exact number of additions AFMM performs on (X, Y) (synchronises)."""
+    total, flags, rc = count_adds_async(case, X, Y, rows)
+    t = int(total.cpu().view(_torch().int64).item()) & ((1 << 64) - 1)
+    out = [t]
+    if rows:
+        out.append(rc)
+    if with_flags:
+        out.append(int(flags.cpu().item()))
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def validate(case, X, Y, mode="strict") -> int:
+    """Synchronous data check; returns the afmm_status code (0 = ok)."""
+    c, n = _operands(case, X, Y)
+    return int(_lib.afmm_validate(c, n, X.data_ptr(), Y.data_ptr(), _mode_id(mode), _stream()))
+
+
+def default_config(case, n):
+    return _lib.afmm_default_config(_case_id(case), n).as_tuple()
+
+
+def config_supported(case, cfg) -> bool:
+    c = cfg if isinstance(cfg, afmm_config) else afmm_config(*cfg)
+    return bool(_lib.afmm_config_supported(_case_id(case), ctypes.byref(c)))
+
+
+def set_tuning(entries):
+    """entries: iterable of (case, n_lo, n_hi, (mapping, R, C, W))."""
+    entries = list(entries)
+    k = len(entries)
+    cases = (ctypes.c_int32 * max(k, 1))(*[_case_id(e[0]) for e in entries])
+    lo = (ctypes.c_int64 * max(k, 1))(*[e[1] for e in entries])
+    hi = (ctypes.c_int64 * max(k, 1))(*[e[2] for e in entries])
+    cfgs = (afmm_config * max(k, 1))(*[afmm_config(*e[3]) for e in entries])
+    _check("set_tuning", _lib.afmm_set_tuning(k, cases, lo, hi, cfgs))
+
+
+def load_tuning(path=None):
+    """Load a tuning table written by the autotuner (JSON), if present."""
+    import json
+    path = path or os.environ.get("AFMM_TUNE_CACHE", os.path.join(_HERE, "tune_cache.json"))
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        d = json.load(f)
+    set_tuning((e["case"], e["n_lo"], e["n_hi"], tuple(e["config"])) for e in d["entries"])
+    return True
+
+
+class Plan:
+    """A batch of independent products run by one persistent launch (strict mode)."""
+
+    def __init__(self, problems, mode="strict"):
+        """problems: list of (case, X, Y, Z) device tensors."""
+        k = len(problems)
+        arr = (afmm_problem * max(k, 1))()
+        self._keep = problems
+        for t, (case, X, Y, Z) in enumerate(problems):
+            c, n = _operands(case, X, Y)
+            arr[t] = afmm_problem(c, n, X.data_ptr(), Y.data_ptr(), Z.data_ptr())
+        h = ctypes.c_void_p()
+        _check("plan_create", _lib.afmm_plan_create(arr, k, _mode_id(mode), ctypes.byref(h)))
+        self._h = h
+        self.count = k
+
+    def launch(self):
+        _check("plan_launch", _lib.afmm_plan_launch(self._h, _stream()))
+
+    def problem_adds(self):
+        """Per-problem addition counts of the last launch (synchronises)."""
+        torch = _torch()
+        out = torch.empty(self.count, dtype=torch.int64, device="cuda")
+        _check("plan_problem_adds", _lib.afmm_plan_problem_adds(self._h, out.data_ptr(), _stream()))
+        return [int(v) & ((1 << 64) - 1) for v in out.cpu().tolist()]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.afmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+try:
+    load_tuning()
+except Exception:  # a malformed cache must not break import; the built-in rule applies
+    pass

@@ -1,0 +1,378 @@
+// C ABI of libafmm (include/afmm.h): argument checks, workspace layout,
+// kernel choice and launch order.  No arithmetic of the method happens here.
+#include "afmm.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace afmm;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+afmm_status hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return AFMM_ERR_HIP;
+}
+
+#define AFMM_HIP(call)                                   \
+    do {                                                 \
+        const hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_);       \
+    } while (0)
+
+// ---- device check (once per device) ----------------------------------------
+std::mutex g_dev_mu;
+std::vector<int> g_dev_ok;  // -1 unknown, 0 bad, 1 gfx950
+
+afmm_status check_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return AFMM_ERR_NO_DEVICE;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if ((int)g_dev_ok.size() <= dev) g_dev_ok.resize(dev + 1, -1);
+    if (g_dev_ok[dev] < 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return AFMM_ERR_NO_DEVICE;
+        g_dev_ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    }
+    return g_dev_ok[dev] ? AFMM_OK : AFMM_ERR_NO_DEVICE;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+afmm_status check_args(int64_t n, const void* X, const void* Y, const void* Z) {
+    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !Z) return AFMM_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)n * (size_t)n * 4;
+    if (overlaps(Z, bytes, X, bytes) || overlaps(Z, bytes, Y, bytes)) return AFMM_ERR_ALIAS;
+    if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
+         reinterpret_cast<uintptr_t>(Z)) & 3)
+        return AFMM_ERR_INVALID_ARG;
+    return AFMM_OK;
+}
+
+// ---- workspace layout -------------------------------------------------------
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) / 256 * 256;
+        return at;
+    }
+};
+
+struct StrictLayout {
+    int rows_pad;
+    int64_t ldp, ldq;
+    size_t p8, xt, esc, total;
+};
+
+StrictLayout strict_layout(afmm_case c, int64_t n) {
+    StrictLayout L;
+    L.rows_pad = (int)round_up(n, kRowPad);
+    L.ldp = round_up(n, kKPad);
+    L.ldq = round_up(n, 64);
+    Carve cv;
+    L.p8 = cv.take((size_t)L.rows_pad * L.ldp);
+    L.xt = c == AFMM_CASE_A ? cv.take((size_t)round_up(n, kKPad) * L.ldq * 4) : 0;
+    L.esc = cv.take(4);
+    L.total = cv.off;
+    return L;
+}
+
+struct SplitLayout {
+    int rows_pad;
+    int64_t ld;
+    size_t planes[4], total;  // three real-term planes, then the integer plane
+};
+
+SplitLayout split_layout(int64_t n) {
+    SplitLayout L;
+    L.rows_pad = split_rows_pad((int)n);
+    L.ld = round_up(n, 64);
+    Carve cv;
+    for (int p = 0; p < 4; ++p) L.planes[p] = cv.take((size_t)L.rows_pad * L.ld * 2);
+    L.total = cv.off;
+    return L;
+}
+
+size_t count_ws(int64_t n) { return (size_t)round_up(n * 8, 256) + 256 + 256; }
+
+// Workspace from the caller or from the stream-ordered allocator.
+struct Scratch {
+    void* ptr = nullptr;
+    bool owned = false;
+    hipStream_t s = nullptr;
+    afmm_status get(void* ws, size_t ws_bytes, size_t need, hipStream_t stream) {
+        s = stream;
+        if (ws) {
+            if (ws_bytes < need) return AFMM_ERR_WORKSPACE;
+            ptr = ws;
+            return AFMM_OK;
+        }
+        const hipError_t e = hipMallocAsync(&ptr, need, stream);
+        if (e != hipSuccess) return hip_fail(e);
+        owned = true;
+        return AFMM_OK;
+    }
+    ~Scratch() {
+        if (owned) (void)hipFreeAsync(ptr, s);
+    }
+    uint8_t* at(size_t off) const { return static_cast<uint8_t*>(ptr) + off; }
+};
+
+// ---- strict configurations --------------------------------------------------
+struct TuneEntry {
+    int32_t c;
+    int64_t lo, hi;
+    afmm_config cfg;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+bool config_ok(afmm_case c, const afmm_config& g) {
+    if (g.mapping == 0) return rep_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
+    if (g.mapping == 1)
+        return c == AFMM_CASE_A && base_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
+    return false;
+}
+
+// Built-in rule: the biggest tile that still gives two workgroups per compute
+// unit (512 tiles on 256 CUs); small problems fall back to small tiles.
+afmm_config builtin_config(int64_t n) {
+    static const int cand[][3] = {{8, 8, 8}, {8, 4, 8}, {4, 4, 8}, {8, 4, 4},
+                                  {4, 4, 4}, {4, 2, 4}, {2, 1, 4}};
+    for (const auto& k : cand) {
+        const int64_t tm = (int64_t)k[0] * k[2], tn = 64LL * k[1];
+        const int64_t tiles = ((n + tm - 1) / tm) * ((n + tn - 1) / tn);
+        if (tiles >= 512 && n >= tn / 2) return afmm_config{0, k[0], k[1], k[2]};
+    }
+    if (n >= 256) return afmm_config{0, 4, 4, 4};
+    if (n >= 128) return afmm_config{0, 4, 2, 4};
+    return afmm_config{0, 2, 1, 4};
+}
+
+afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
+                       const afmm_config& cfg, void* ws, size_t ws_bytes, hipStream_t s) {
+    const StrictLayout L = strict_layout(c, n);
+    Scratch sc;
+    const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
+    if (st != AFMM_OK) return st;
+    uint8_t* P8 = sc.at(L.p8);
+    uint32_t* esc = reinterpret_cast<uint32_t*>(sc.at(L.esc));
+    StrictArgs a{};
+    a.n_r = a.n_c = a.n_k = (int)n;
+    a.P8 = P8;
+    a.ldp = L.ldp;
+    a.Z = Z;
+    a.esc = esc;
+    if (c == AFMM_CASE_B) {
+        // rows i carry the counts X[i,k]; lanes over j read Y[k,j]
+        AFMM_HIP(launch_pack_rows(static_cast<const int32_t*>(X), (int)n, P8, L.ldp, L.rows_pad,
+                                  esc, s));
+        a.P32 = static_cast<const int32_t*>(X);
+        a.p32_sr = n;
+        a.p32_sk = 1;
+        a.Q = static_cast<const float*>(Y);
+        a.ldq = n;
+        a.z_sr = n;
+        a.z_sc = 1;
+        a.trans_out = false;
+        a.q_padded = false;
+    } else {
+        // transposed problem: rows j carry the counts Y[k,j]; lanes over i read X[i,k]
+        float* Xt = reinterpret_cast<float*>(sc.at(L.xt));
+        AFMM_HIP(launch_pack_transpose(static_cast<const int32_t*>(Y), (int)n, P8, L.ldp,
+                                       L.rows_pad, esc, s));
+        AFMM_HIP(launch_transpose_f32(static_cast<const float*>(X), (int)n, Xt, L.ldq,
+                                      (int)round_up(n, kKPad), s));
+        a.P32 = static_cast<const int32_t*>(Y);
+        a.p32_sr = 1;
+        a.p32_sk = n;
+        a.Q = Xt;
+        a.ldq = L.ldq;
+        a.z_sr = 1;
+        a.z_sc = n;
+        a.trans_out = true;
+        a.q_padded = true;
+    }
+    if (cfg.mapping == 0) {
+        AFMM_HIP(launch_rep_uniform(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
+    } else {
+        BaseUniformArgs b{(int)n, static_cast<const float*>(X), static_cast<const int32_t*>(Y), Z};
+        AFMM_HIP(launch_base_uniform(b, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
+    }
+    return AFMM_OK;
+}
+
+afmm_status split_run(afmm_case c, int64_t n, const void* X, const void* Y, float* Z, void* ws,
+                      size_t ws_bytes, hipStream_t s) {
+    const SplitLayout L = split_layout(n);
+    Scratch sc;
+    const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
+    if (st != AFMM_OK) return st;
+    uint16_t* P[4];
+    for (int p = 0; p < 4; ++p) P[p] = reinterpret_cast<uint16_t*>(sc.at(L.planes[p]));
+    if (c == AFMM_CASE_A) {
+        // A operand: X's three terms [i][k]; B operand: Y as bf16 turned to [j][k]
+        AFMM_HIP(launch_split_real(static_cast<const float*>(X), (int)n, false, P[0], P[1], P[2],
+                                   L.ld, L.rows_pad, s));
+        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(Y), (int)n, true, P[3], L.ld,
+                                    L.rows_pad, s));
+        AFMM_HIP(launch_gemm_bf16x3((int)n, P[0], P[1], P[2], P[3], P[3], P[3], L.ld, Z, s));
+    } else {
+        // A operand: X as bf16 [i][k]; B operand: Y's three terms turned to [j][k]
+        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(X), (int)n, false, P[3], L.ld,
+                                    L.rows_pad, s));
+        AFMM_HIP(launch_split_real(static_cast<const float*>(Y), (int)n, true, P[0], P[1], P[2],
+                                   L.ld, L.rows_pad, s));
+        AFMM_HIP(launch_gemm_bf16x3((int)n, P[3], P[3], P[3], P[0], P[1], P[2], L.ld, Z, s));
+    }
+    return AFMM_OK;
+}
+
+afmm_status multiply(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
+                     afmm_mode mode, void* ws, size_t ws_bytes, hipStream_t s) {
+    afmm_status st = check_args(n, X, Y, Z);
+    if (st != AFMM_OK) return st;
+    if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;
+    if ((st = check_device()) != AFMM_OK) return st;
+    if (mode == AFMM_MODE_STRICT) return strict_run(c, n, X, Y, Z, afmm_default_config(c, n), ws,
+                                                    ws_bytes, s);
+    return split_run(c, n, X, Y, Z, ws, ws_bytes, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode) {
+    if (n < 1 || n > AFMM_MAX_N || (c != AFMM_CASE_A && c != AFMM_CASE_B)) return 0;
+    if (mode == AFMM_MODE_SPLIT_BF16X3) return split_layout(n).total;
+    return std::max(strict_layout(c, n).total, count_ws(n));
+}
+
+afmm_status afmm_multiply_caseA(int64_t n, const float* X, const int32_t* Y, float* Z,
+                                afmm_mode mode, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+    return multiply(AFMM_CASE_A, n, X, Y, Z, mode, workspace, workspace_bytes, stream);
+}
+
+afmm_status afmm_multiply_caseB(int64_t n, const int32_t* X, const float* Y, float* Z,
+                                afmm_mode mode, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+    return multiply(AFMM_CASE_B, n, X, Y, Z, mode, workspace, workspace_bytes, stream);
+}
+
+afmm_status afmm_count_adds(afmm_case c, int64_t n, const void* X, const void* Y,
+                            uint64_t* d_total, uint64_t* d_row_counts, uint32_t* d_flags,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !d_total || (c != AFMM_CASE_A && c != AFMM_CASE_B))
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    Scratch sc;
+    if ((st = sc.get(workspace, workspace_bytes, count_ws(n), stream)) != AFMM_OK) return st;
+    uint64_t* wk = reinterpret_cast<uint64_t*>(sc.at(0));
+    uint32_t* flags = d_flags ? d_flags
+                              : reinterpret_cast<uint32_t*>(sc.at((size_t)round_up(n * 8, 256)));
+    AFMM_HIP(launch_count((int)c, (int)n, X, Y, wk, d_row_counts, d_total, flags, stream));
+    return AFMM_OK;
+}
+
+afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, afmm_mode mode,
+                          hipStream_t stream) {
+    if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;
+    if (n < 1 || n > AFMM_MAX_N || !X || !Y || (c != AFMM_CASE_A && c != AFMM_CASE_B))
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    void* buf = nullptr;
+    const size_t need = count_ws(n) + 256;
+    AFMM_HIP(hipMallocAsync(&buf, need, stream));
+    uint8_t* b = static_cast<uint8_t*>(buf);
+    uint64_t* total = reinterpret_cast<uint64_t*>(b + count_ws(n));
+    uint32_t* flags = reinterpret_cast<uint32_t*>(b + count_ws(n) + 8);
+    st = afmm_count_adds(c, n, X, Y, total, nullptr, flags, b, count_ws(n), stream);
+    uint32_t hflags = 0;
+    if (st == AFMM_OK) {
+        hipError_t e = hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) st = hip_fail(e);
+    }
+    (void)hipFreeAsync(buf, stream);
+    if (st != AFMM_OK) return st;
+    if (hflags & AFMM_FLAG_NEGATIVE) return AFMM_ERR_NEGATIVE_INT;
+    if (mode == AFMM_MODE_SPLIT_BF16X3 && (hflags & AFMM_FLAG_ABOVE256)) return AFMM_ERR_INT_RANGE;
+    if (hflags & AFMM_FLAG_OVERFLOW) return AFMM_ERR_COUNT_OVERFLOW;
+    return AFMM_OK;
+}
+
+int afmm_config_supported(afmm_case c, const afmm_config* cfg) {
+    if (!cfg || (c != AFMM_CASE_A && c != AFMM_CASE_B)) return 0;
+    return config_ok(c, *cfg) ? 1 : 0;
+}
+
+afmm_config afmm_default_config(afmm_case c, int64_t n) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+            if (it->c == (int32_t)c && n >= it->lo && n <= it->hi) return it->cfg;
+    }
+    return builtin_config(n);
+}
+
+afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void* X, const void* Y,
+                                        float* Z, const afmm_config* cfg, void* workspace,
+                                        size_t workspace_bytes, hipStream_t stream) {
+    if (c != AFMM_CASE_A && c != AFMM_CASE_B) return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_args(n, X, Y, Z);
+    if (st != AFMM_OK) return st;
+    if (!cfg || !config_ok(c, *cfg)) return AFMM_ERR_INVALID_ARG;
+    if ((st = check_device()) != AFMM_OK) return st;
+    return strict_run(c, n, X, Y, Z, *cfg, workspace, workspace_bytes, stream);
+}
+
+afmm_status afmm_set_tuning(int32_t count, const int32_t* cases, const int64_t* n_lo,
+                            const int64_t* n_hi, const afmm_config* cfgs) {
+    if (count < 0 || (count > 0 && (!cases || !n_lo || !n_hi || !cfgs))) return AFMM_ERR_INVALID_ARG;
+    std::vector<TuneEntry> t;
+    for (int32_t i = 0; i < count; ++i) {
+        if (cases[i] != AFMM_CASE_A && cases[i] != AFMM_CASE_B) return AFMM_ERR_INVALID_ARG;
+        if (!config_ok((afmm_case)cases[i], cfgs[i]) || n_lo[i] > n_hi[i]) return AFMM_ERR_INVALID_ARG;
+        t.push_back(TuneEntry{cases[i], n_lo[i], n_hi[i], cfgs[i]});
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.swap(t);
+    return AFMM_OK;
+}
+
+const char* afmm_status_string(afmm_status s) {
+    switch (s) {
+    case AFMM_OK: return "ok";
+    case AFMM_ERR_INVALID_ARG: return "invalid argument";
+    case AFMM_ERR_ALIAS: return "output overlaps an input";
+    case AFMM_ERR_NEGATIVE_INT: return "negative integer entry";
+    case AFMM_ERR_INT_RANGE: return "integer entry out of range for the split form";
+    case AFMM_ERR_COUNT_OVERFLOW: return "addition count exceeds 2^64-1";
+    case AFMM_ERR_NO_DEVICE: return "no gfx950 device";
+    case AFMM_ERR_HIP: return "HIP error";
+    case AFMM_ERR_UNSUPPORTED: return "unsupported";
+    case AFMM_ERR_WORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+int afmm_last_hip_error(void) { return g_last_hip; }
+
+const char* afmm_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Shared device helpers and host launcher declarations of libafmm (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace afmm {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies, own L2 each
+constexpr int kRowPad = 64;      // packed-count rows are padded to this multiple
+constexpr int kKPad = 64;        // and the reduction axis too
+
+static inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Workgroups of a 1-D grid are dealt to the XCDs round-robin (block b runs on
+// XCD b % 8).  Renumber so that each XCD receives one contiguous run of the
+// logical tile order; tiles that share operand panels then share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int n_tiles) {
+    const int per = n_tiles / kXcds, rem = n_tiles % kXcds;
+    const int xcd = bid % kXcds, local = bid / kXcds;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Saturating byte of a repetition count: <= 0 -> 0 (no additions), 1..254 as
+// is, >= 255 -> 255, which tells the kernel to re-read the full int32 count.
+__device__ __forceinline__ uint32_t count_byte(int32_t v) {
+    return v <= 0 ? 0u : (v >= 255 ? 255u : (uint32_t)v);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (each returns the hipError_t of its launch).
+
+// prep.hip
+// Both clear *esc first and set it when some count byte is 255.
+hipError_t launch_pack_rows(const int32_t* I, int n, uint8_t* P8, int64_t ldp, int rows_pad,
+                            uint32_t* esc, hipStream_t s);
+hipError_t launch_pack_transpose(const int32_t* I, int n, uint8_t* P8, int64_t ldp,
+                                 int rows_pad, uint32_t* esc, hipStream_t s);
+hipError_t launch_transpose_f32(const float* X, int n, float* Xt, int64_t ldq, int rows_pad,
+                                hipStream_t s);
+hipError_t launch_count(int case_id, int n, const void* X, const void* Y, uint64_t* wk,
+                        uint64_t* rows, uint64_t* total, uint32_t* flags, hipStream_t s);
+
+// strict.hip
+struct StrictArgs {
+    int n_r, n_c, n_k;                       // rows (count-uniform), lanes, reduction
+    const uint8_t* P8; int64_t ldp;          // packed counts [rows_pad x ldp]
+    const int32_t* P32; int64_t p32_sr, p32_sk;  // original counts (escape 255)
+    const float* Q; int64_t ldq;             // base rows k, contiguous over lanes
+    float* Z; int64_t z_sr, z_sc;            // output (r, c) at r*z_sr + c*z_sc
+    const uint32_t* esc;                     // device word: non-zero if a byte is 255
+    bool trans_out;                          // z_sr == 1: output (r, c) at c*z_sc + r
+    bool q_padded;                           // Q rows readable up to round_up(n_c, 4)
+};
+hipError_t launch_rep_uniform(const StrictArgs& a, int R, int C, int W, hipStream_t s);
+bool rep_uniform_supported(int R, int C, int W);
+
+struct BaseUniformArgs {
+    int n;
+    const float* X;          // rows i, base X[i,k] (wave-uniform)
+    const int32_t* Y;        // per-lane counts Y[k,j]
+    float* Z;
+};
+hipError_t launch_base_uniform(const BaseUniformArgs& a, int R, int C, int W, hipStream_t s);
+bool base_uniform_supported(int R, int C, int W);
+
+// split.hip
+hipError_t launch_split_real(const float* R, int n, bool transpose, uint16_t* hi, uint16_t* mid,
+                             uint16_t* lo, int64_t ld, int rows_pad, hipStream_t s);
+hipError_t launch_int_to_bf16(const int32_t* I, int n, bool transpose, uint16_t* out, int64_t ld,
+                              int rows_pad, hipStream_t s);
+hipError_t launch_gemm_bf16x3(int n, const uint16_t* A0, const uint16_t* A1, const uint16_t* A2,
+                              const uint16_t* B0, const uint16_t* B1, const uint16_t* B2,
+                              int64_t ld, float* Z, hipStream_t s);
+int split_rows_pad(int n);
+
+}  // namespace afmm

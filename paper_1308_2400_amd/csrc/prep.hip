@@ -1,0 +1,242 @@
+// Operand preparation and addition counting (HBM-bound passes).
+//
+//  * pack_rows / pack_transpose: the integer factor as saturated count bytes,
+//    laid out so that the strict kernel reads one row of counts per output
+//    row with scalar loads (4 counts per dword).
+//  * transpose_f32: case A's real factor turned so that the strict kernel's
+//    lanes read it contiguously.
+//  * count: the exact addition count of Section 2.2 (per row and total) and
+//    the data flags, in integer arithmetic.
+#include "common.hpp"
+
+namespace afmm {
+
+// ---------------------------------------------------------------------------
+// P8[r][k] = count_byte(I[r][k]) for r, k < n; zero on the padding.
+// One thread per output dword (4 counts).
+__global__ void zero_u32_kernel(uint32_t* w) { *w = 0; }
+
+__global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restrict__ I, int n,
+                                                       uint8_t* __restrict__ P8, int64_t ldp,
+                                                       int rows_pad, uint32_t* __restrict__ esc) {
+    bool hit = false;
+    const int64_t words_per_row = ldp / 4;
+    const int64_t total = (int64_t)rows_pad * words_per_row;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < total;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = w / words_per_row;
+        const int64_t k = (w - r * words_per_row) * 4;
+        uint32_t word = 0;
+        if (r < n) {
+            const int32_t* src = I + r * n;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (k + t < n) {
+                    const uint32_t c = count_byte(src[k + t]);
+                    hit |= c == 255u;
+                    word |= c << (8 * t);
+                }
+        }
+        reinterpret_cast<uint32_t*>(P8)[w] = word;
+    }
+    if (hit) atomicOr(esc, 1u);
+}
+
+// P8[j][k] = count_byte(I[k][j]): 64 x 64 tiles through LDS.  Block (64, 4).
+__global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __restrict__ I, int n,
+                                                            uint8_t* __restrict__ P8,
+                                                            int64_t ldp, uint32_t* __restrict__ esc) {
+    __shared__ uint8_t tile[64][64 + 4];
+    bool hit = false;
+    const int j0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    for (int kr = ty; kr < 64; kr += 4) {
+        const int k = k0 + kr, j = j0 + tx;
+        const uint32_t c = (k < n && j < n) ? count_byte(I[(int64_t)k * n + j]) : 0u;
+        hit |= c == 255u;
+        tile[kr][tx] = (uint8_t)c;
+    }
+    if (hit) atomicOr(esc, 1u);
+    __syncthreads();
+    // 64 rows j x 16 dwords along k
+    const int tid = ty * 64 + tx;
+    for (int e = tid; e < 64 * 16; e += 256) {
+        const int jr = e / 16, q = e % 16;
+        const uint32_t word = (uint32_t)tile[4 * q][jr] | ((uint32_t)tile[4 * q + 1][jr] << 8) |
+                              ((uint32_t)tile[4 * q + 2][jr] << 16) |
+                              ((uint32_t)tile[4 * q + 3][jr] << 24);
+        reinterpret_cast<uint32_t*>(P8 + (int64_t)(j0 + jr) * ldp + k0)[q] = word;
+    }
+}
+
+// Xt[k][i] = X[i][k] for i, k < n; zero on the padding.  Block (64, 4).
+__global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restrict__ X, int n,
+                                                           float* __restrict__ Xt, int64_t ldq) {
+    __shared__ float tile[64][64 + 1];
+    const int i0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    for (int ir = ty; ir < 64; ir += 4) {
+        const int i = i0 + ir, k = k0 + tx;
+        tile[ir][tx] = (i < n && k < n) ? X[(int64_t)i * n + k] : 0.0f;
+    }
+    __syncthreads();
+    for (int kr = ty; kr < 64; kr += 4) Xt[(int64_t)(k0 + kr) * ldq + i0 + tx] = tile[tx][kr];
+}
+
+hipError_t launch_pack_rows(const int32_t* I, int n, uint8_t* P8, int64_t ldp, int rows_pad,
+                            uint32_t* esc, hipStream_t s) {
+    const int64_t words = (int64_t)rows_pad * (ldp / 4);
+    const int grid = (int)std::min<int64_t>((words + 255) / 256, 65536);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
+    hipLaunchKernelGGL(pack_rows_kernel, dim3(grid), dim3(256), 0, s, I, n, P8, ldp, rows_pad,
+                       esc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_transpose(const int32_t* I, int n, uint8_t* P8, int64_t ldp,
+                                 int rows_pad, uint32_t* esc, hipStream_t s) {
+    dim3 grid(rows_pad / 64, (unsigned)(ldp / 64));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
+    hipLaunchKernelGGL(pack_transpose_kernel, grid, dim3(64, 4), 0, s, I, n, P8, ldp, esc);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_f32(const float* X, int n, float* Xt, int64_t ldq, int rows_pad,
+                                hipStream_t s) {
+    // Xt has rows_pad rows (k) and ldq columns (i); both multiples of 64.
+    dim3 grid((unsigned)(ldq / 64), rows_pad / 64);
+    hipLaunchKernelGGL(transpose_f32_kernel, grid, dim3(64, 4), 0, s, X, n, Xt, ldq);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Counting.  Flag bits as in afmm.h.
+constexpr uint32_t kNeg = 1u, kAbove255 = 2u, kAbove256 = 4u, kOverflow = 8u;
+
+__device__ __forceinline__ uint32_t int_flags(int32_t v) {
+    return (v < 0 ? kNeg : 0u) | (v > 255 ? kAbove255 : 0u) | (v > 256 ? kAbove256 : 0u);
+}
+
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b, uint32_t& fl) {
+    uint64_t r;
+    if (__builtin_add_overflow(a, b, &r)) {
+        fl |= kOverflow;
+        return ~0ull;
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b, uint32_t& fl) {
+    uint64_t r;
+    if (__builtin_mul_overflow(a, b, &r)) {
+        fl |= kOverflow;
+        return ~0ull;
+    }
+    return r;
+}
+
+// Saturating sum of a uint64 over the 256 threads of a block; result in thread 0.
+__device__ uint64_t block_sum_sat(uint64_t v, uint32_t& fl) {
+    __shared__ uint64_t part[4];
+    __shared__ uint32_t pfl[4];
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_down(v, off, 64);
+        if ((threadIdx.x & 63) + off < 64) v = sat_add(v, o, fl);
+    }
+    for (int off = 32; off > 0; off >>= 1) fl |= __shfl_down(fl, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[w] = v;
+        pfl[w] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = part[0];
+        fl = pfl[0];
+        for (int t = 1; t < 4; ++t) {
+            fl |= pfl[t];
+            v = sat_add(v, part[t], fl);
+        }
+    }
+    return v;
+}
+
+__global__ void count_zero_kernel(uint64_t* total, uint32_t* flags) {
+    *total = 0;
+    *flags = 0;
+}
+
+// wk[k] = weight of row k of the post-factor Y:
+//   case A: sum_j max(Y[k,j], 0)     (Y integer; < n * 2^31, no overflow)
+//   case B: #{j : Y[k,j] != 0}       (Y real)
+__global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, const void* __restrict__ Yv,
+                                                         uint64_t* __restrict__ wk,
+                                                         uint32_t* __restrict__ flags) {
+    const int k = blockIdx.x;
+    uint64_t s = 0;
+    uint32_t fl = 0;
+    if (case_id == 0) {
+        const int32_t* y = (const int32_t*)Yv + (int64_t)k * n;
+        for (int j = threadIdx.x; j < n; j += 256) {
+            const int32_t v = y[j];
+            fl |= int_flags(v);
+            if (v > 0) s += (uint64_t)v;
+        }
+    } else {
+        const float* y = (const float*)Yv + (int64_t)k * n;
+        for (int j = threadIdx.x; j < n; j += 256) s += (y[j] != 0.0f) ? 1u : 0u;
+    }
+    s = block_sum_sat(s, fl);
+    if (threadIdx.x == 0) {
+        wk[k] = s;
+        if (fl) atomicOr(flags, fl);
+    }
+}
+
+// Row counts of Section 2.2 summed exactly:
+//   case A: r_i = sum_k [X[i,k] != 0] * wk[k]
+//   case B: r_i = sum_k max(X[i,k], 0) * wk[k]
+__global__ __launch_bounds__(256) void count_rows_kernel(int case_id, int n, const void* __restrict__ Xv,
+                                                        const uint64_t* __restrict__ wk,
+                                                        uint64_t* __restrict__ rows,
+                                                        uint64_t* __restrict__ total,
+                                                        uint32_t* __restrict__ flags) {
+    const int i = blockIdx.x;
+    uint64_t s = 0;
+    uint32_t fl = 0;
+    if (case_id == 0) {
+        const float* x = (const float*)Xv + (int64_t)i * n;
+        for (int k = threadIdx.x; k < n; k += 256)
+            if (x[k] != 0.0f) s = sat_add(s, wk[k], fl);
+    } else {
+        const int32_t* x = (const int32_t*)Xv + (int64_t)i * n;
+        for (int k = threadIdx.x; k < n; k += 256) {
+            const int32_t v = x[k];
+            fl |= int_flags(v);
+            if (v > 0) s = sat_add(s, sat_mul((uint64_t)v, wk[k], fl), fl);
+        }
+    }
+    s = block_sum_sat(s, fl);
+    if (threadIdx.x == 0) {
+        if (rows) rows[i] = s;
+        const unsigned long long old = atomicAdd((unsigned long long*)total, (unsigned long long)s);
+        if (old + s < old) fl |= kOverflow;
+        if (fl) atomicOr(flags, fl);
+    }
+}
+
+__global__ void count_finalize_kernel(uint64_t* total, const uint32_t* flags) {
+    if (*flags & kOverflow) *total = ~0ull;
+}
+
+hipError_t launch_count(int case_id, int n, const void* X, const void* Y, uint64_t* wk,
+                        uint64_t* rows, uint64_t* total, uint32_t* flags, hipStream_t s) {
+    hipLaunchKernelGGL(count_zero_kernel, dim3(1), dim3(1), 0, s, total, flags);
+    hipLaunchKernelGGL(count_kstat_kernel, dim3(n), dim3(256), 0, s, case_id, n, Y, wk, flags);
+    hipLaunchKernelGGL(count_rows_kernel, dim3(n), dim3(256), 0, s, case_id, n, X, wk, rows,
+                       total, flags);
+    hipLaunchKernelGGL(count_finalize_kernel, dim3(1), dim3(1), 0, s, total, flags);
+    return hipGetLastError();
+}
+
+}  // namespace afmm

