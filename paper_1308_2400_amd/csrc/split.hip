@@ -123,49 +123,70 @@ hipError_t launch_int_to_bf16(const int32_t* I, int n, bool transpose, uint16_t*
 // MFMA 32x32x16 operand layout: lane l supplies row (l % 32) of A (column
 // (l % 32) of B) and the eight K values 8*(l / 32) .. +7 of the 16; result
 // register v of lane l holds row 8*(v / 4) + 4*(l / 32) + v % 4, column l % 32.
+constexpr int kPlane = kGM * kLdsRow;  // bf16 per plane tile in LDS
+
+// Tile order: each XCD gets a contiguous run of tiles (xcd_remap), and inside
+// it tiles go column-band-major in groups of kGroupM row tiles so that blocks
+// running together share both operand panels in that XCD's L2.
+constexpr int kGroupM = 8;
+
+__device__ __forceinline__ void gemm_tile_coords(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
+    const int per_group = kGroupM * tiles_n;
+    const int g = t / per_group, first_m = g * kGroupM;
+    const int gm = min(tiles_m - first_m, kGroupM);
+    const int r = t - g * per_group;
+    tm = first_m + r % gm;
+    tn = r / gm;
+}
+
 template <bool TRIPLE_A>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(
+__global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     int n, const uint16_t* __restrict__ A0, const uint16_t* __restrict__ A1,
     const uint16_t* __restrict__ A2, const uint16_t* __restrict__ B0,
     const uint16_t* __restrict__ B1, const uint16_t* __restrict__ B2, int64_t ld,
-    float* __restrict__ Z, int tiles_m, int n_tiles) {
-    constexpr int NA = TRIPLE_A ? 3 : 1, NB = TRIPLE_A ? 1 : 3;
-    constexpr int PLANE = kGM * kLdsRow;              // bf16 per plane tile
-    constexpr int STAGE = (NA + NB) * PLANE;
+    float* __restrict__ Z, int tiles_m, int tiles_n) {
+    // LDS stage: planes 0..2 = the split side (hi, mid, lo), plane 3 = the other side
+    constexpr int STAGE = 4 * kPlane;
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * STAGE];
 
-    const int t = xcd_remap(blockIdx.x, n_tiles);
-    const int tn = t / tiles_m, tm = t - tn * tiles_m;
+    int tm, tn;
+    gemm_tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, tm, tn);
     const int m0 = tm * kGM, c0 = tn * kGN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * 64, wc = (wave >> 1) * 64;
 
-    const uint16_t* ap[3] = {A0, A1, A2};
-    const uint16_t* bp[3] = {B0, B1, B2};
+    // split side rows start at s0 (m0 for TRIPLE_A, c0 otherwise); the other side at o0
+    const int s0 = TRIPLE_A ? m0 : c0, o0 = TRIPLE_A ? c0 : m0;
+    const uint16_t* S0 = TRIPLE_A ? A0 : B0;
+    const uint16_t* S1 = TRIPLE_A ? A1 : B1;
+    const uint16_t* S2 = TRIPLE_A ? A2 : B2;
+    const uint16_t* O = TRIPLE_A ? B0 : A0;
 
-    // Global -> LDS staging: each plane tile is 128 rows x 32 K = 512 chunks of
-    // 8 bf16; thread tid moves chunks tid and tid + 256 of every plane.
-    uint4 stg[(NA + NB) * 2];
-    auto load_stage = [&](int k0) {
-#pragma unroll
-        for (int p = 0; p < NA + NB; ++p)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ch = tid + h * 256, row = ch >> 2, kc = (ch & 3) * 8;
-                const uint16_t* base = p < NA ? ap[p] + (int64_t)(m0 + row) * ld
-                                              : bp[p - NA] + (int64_t)(c0 + row) * ld;
-                stg[p * 2 + h] = *reinterpret_cast<const uint4*>(base + k0 + kc);
-            }
-    };
-    auto store_stage = [&](uint16_t* dst) {
-#pragma unroll
-        for (int p = 0; p < NA + NB; ++p)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ch = tid + h * 256, row = ch >> 2, kc = (ch & 3) * 8;
-                *reinterpret_cast<uint4*>(dst + p * PLANE + row * kLdsRow + kc) = stg[p * 2 + h];
-            }
-    };
+    // Global -> LDS staging: a plane tile is 128 rows x 32 K = 512 chunks of 8 bf16;
+    // thread tid moves chunks tid and tid + 256 of each of the four planes.
+    const int row_a = tid >> 2, row_b = row_a + 64, kc = (tid & 3) * 8;
+    const int64_t sa = (int64_t)(s0 + row_a) * ld + kc, sb = (int64_t)(s0 + row_b) * ld + kc;
+    const int64_t oa = (int64_t)(o0 + row_a) * ld + kc, ob = (int64_t)(o0 + row_b) * ld + kc;
+    const int la = row_a * kLdsRow + kc, lb = row_b * kLdsRow + kc;
+    uint4 g0a, g0b, g1a, g1b, g2a, g2b, goa, gob;
+#define AFMM_GLOAD(k0)                                                     \
+    g0a = *reinterpret_cast<const uint4*>(S0 + sa + (k0));                 \
+    g0b = *reinterpret_cast<const uint4*>(S0 + sb + (k0));                 \
+    g1a = *reinterpret_cast<const uint4*>(S1 + sa + (k0));                 \
+    g1b = *reinterpret_cast<const uint4*>(S1 + sb + (k0));                 \
+    g2a = *reinterpret_cast<const uint4*>(S2 + sa + (k0));                 \
+    g2b = *reinterpret_cast<const uint4*>(S2 + sb + (k0));                 \
+    goa = *reinterpret_cast<const uint4*>(O + oa + (k0));                  \
+    gob = *reinterpret_cast<const uint4*>(O + ob + (k0));
+#define AFMM_LSTORE(dst)                                                   \
+    *reinterpret_cast<uint4*>((dst) + 0 * kPlane + la) = g0a;              \
+    *reinterpret_cast<uint4*>((dst) + 0 * kPlane + lb) = g0b;              \
+    *reinterpret_cast<uint4*>((dst) + 1 * kPlane + la) = g1a;              \
+    *reinterpret_cast<uint4*>((dst) + 1 * kPlane + lb) = g1b;              \
+    *reinterpret_cast<uint4*>((dst) + 2 * kPlane + la) = g2a;              \
+    *reinterpret_cast<uint4*>((dst) + 2 * kPlane + lb) = g2b;              \
+    *reinterpret_cast<uint4*>((dst) + 3 * kPlane + la) = goa;              \
+    *reinterpret_cast<uint4*>((dst) + 3 * kPlane + lb) = gob;
 
     f32x16 acc_hi[2][2], acc_lo[2][2];
 #pragma unroll
@@ -179,45 +200,55 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(
             }
 
     const int n_k = (int)(ld / kGK);
-    load_stage(0);
-    store_stage(lds);
+    AFMM_GLOAD(0)
+    AFMM_LSTORE(lds)
     __syncthreads();
     const int fr = lane & 31, fk = (lane >> 5) * 8;
+    // fragment rows inside the stage: A rows (wm + 32 i + fr), B rows (wc + 32 j + fr)
+    const int ra0 = (wm + fr) * kLdsRow + fk, ra1 = ra0 + 32 * kLdsRow;
+    const int rb0 = (wc + fr) * kLdsRow + fk, rb1 = rb0 + 32 * kLdsRow;
+    // plane of the A operand for term s, and of the B operand
+    constexpr int PA0 = TRIPLE_A ? 0 : 3, PA1 = TRIPLE_A ? 1 : 3, PA2 = TRIPLE_A ? 2 : 3;
+    constexpr int PB0 = TRIPLE_A ? 3 : 0, PB1 = TRIPLE_A ? 3 : 1, PB2 = TRIPLE_A ? 3 : 2;
     for (int ks = 0; ks < n_k; ++ks) {
         const uint16_t* cur = lds + (ks & 1) * STAGE;
         const bool more = ks + 1 < n_k;
-        if (more) load_stage((ks + 1) * kGK);
+        if (more) {
+            AFMM_GLOAD((ks + 1) * kGK)
+        }
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 16) {
-            bf16x8 a[NA][2], b[NB][2];
-#pragma unroll
-            for (int p = 0; p < NA; ++p)
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    a[p][i] = *reinterpret_cast<const bf16x8*>(
-                        cur + p * PLANE + (wm + i * 32 + fr) * kLdsRow + kk + fk);
-#pragma unroll
-            for (int p = 0; p < NB; ++p)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    b[p][j] = *reinterpret_cast<const bf16x8*>(
-                        cur + (NA + p) * PLANE + (wc + j * 32 + fr) * kLdsRow + kk + fk);
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    // term 0 (hi) alone; terms 2 (lo) then 1 (mid) into the second set
-                    acc_hi[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        a[0][i], b[0][j], acc_hi[i][j], 0, 0, 0);
-                    acc_lo[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        a[TRIPLE_A ? 2 : 0][i], b[TRIPLE_A ? 0 : 2][j], acc_lo[i][j], 0, 0, 0);
-                    acc_lo[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        a[TRIPLE_A ? 1 : 0][i], b[TRIPLE_A ? 0 : 1][j], acc_lo[i][j], 0, 0, 0);
-                }
+#define AFMM_FRAG(plane, off) (*reinterpret_cast<const bf16x8*>(cur + (plane) * kPlane + (off) + kk))
+            const bf16x8 a00 = AFMM_FRAG(PA0, ra0), a01 = AFMM_FRAG(PA0, ra1);
+            const bf16x8 b00 = AFMM_FRAG(PB0, rb0), b01 = AFMM_FRAG(PB0, rb1);
+            // term 0 (hi) into its own accumulators
+            acc_hi[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a00, b00, acc_hi[0][0], 0, 0, 0);
+            acc_hi[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a00, b01, acc_hi[0][1], 0, 0, 0);
+            acc_hi[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a01, b00, acc_hi[1][0], 0, 0, 0);
+            acc_hi[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a01, b01, acc_hi[1][1], 0, 0, 0);
+            // terms 2 (lo) then 1 (mid) into the second set
+            const bf16x8 a20 = AFMM_FRAG(PA2, ra0), a21 = AFMM_FRAG(PA2, ra1);
+            const bf16x8 b20 = AFMM_FRAG(PB2, rb0), b21 = AFMM_FRAG(PB2, rb1);
+            acc_lo[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a20, b20, acc_lo[0][0], 0, 0, 0);
+            acc_lo[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a20, b21, acc_lo[0][1], 0, 0, 0);
+            acc_lo[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a21, b20, acc_lo[1][0], 0, 0, 0);
+            acc_lo[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a21, b21, acc_lo[1][1], 0, 0, 0);
+            const bf16x8 a10 = AFMM_FRAG(PA1, ra0), a11 = AFMM_FRAG(PA1, ra1);
+            const bf16x8 b10 = AFMM_FRAG(PB1, rb0), b11 = AFMM_FRAG(PB1, rb1);
+            acc_lo[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a10, b10, acc_lo[0][0], 0, 0, 0);
+            acc_lo[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a10, b11, acc_lo[0][1], 0, 0, 0);
+            acc_lo[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a11, b10, acc_lo[1][0], 0, 0, 0);
+            acc_lo[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a11, b11, acc_lo[1][1], 0, 0, 0);
+#undef AFMM_FRAG
         }
-        if (more) store_stage(lds + ((ks + 1) & 1) * STAGE);
+        if (more) {
+            uint16_t* nxt = lds + ((ks + 1) & 1) * STAGE;
+            AFMM_LSTORE(nxt)
+        }
         __syncthreads();
     }
+#undef AFMM_GLOAD
+#undef AFMM_LSTORE
 
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -239,10 +270,10 @@ hipError_t launch_gemm_bf16x3(int n, const uint16_t* A0, const uint16_t* A1, con
     const bool triple_a = A0 != A1;
     if (triple_a)
         hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(256), 0, s, n, A0, A1, A2,
-                           B0, B1, B2, ld, Z, tiles_m, n_tiles);
+                           B0, B1, B2, ld, Z, tiles_m, tiles_n);
     else
         hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(256), 0, s, n, A0, A1,
-                           A2, B0, B1, B2, ld, Z, tiles_m, n_tiles);
+                           A2, B0, B1, B2, ld, Z, tiles_m, tiles_n);
     return hipGetLastError();
 }
 
