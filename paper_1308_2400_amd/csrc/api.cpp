@@ -10,14 +10,21 @@
 
 #include "common.hpp"
 
+static int& g_last_hip_error_slot() {
+    static thread_local int e = 0;
+    return e;
+}
+
 using namespace afmm;
+
+namespace afmm {
+void set_last_hip_error(int e) { g_last_hip_error_slot() = e; }
+}  // namespace afmm
 
 namespace {
 
-thread_local int g_last_hip = 0;
-
 afmm_status hip_fail(hipError_t e) {
-    g_last_hip = (int)e;
+    set_last_hip_error((int)e);
     return AFMM_ERR_HIP;
 }
 
@@ -371,7 +378,7 @@ const char* afmm_status_string(afmm_status s) {
     return "unknown status";
 }
 
-int afmm_last_hip_error(void) { return g_last_hip; }
+int afmm_last_hip_error(void) { return g_last_hip_error_slot(); }
 
 const char* afmm_version(void) { return "0.1.0"; }
 

@@ -28,7 +28,35 @@ __device__ __forceinline__ uint32_t count_byte(int32_t v) {
     return v <= 0 ? 0u : (v >= 255 ? 255u : (uint32_t)v);
 }
 
+// Counting helpers.  Flag bits as in afmm.h.
+constexpr uint32_t kNeg = 1u, kAbove255 = 2u, kAbove256 = 4u, kOverflow = 8u;
+
+__device__ __forceinline__ uint32_t int_flags(int32_t v) {
+    return (v < 0 ? kNeg : 0u) | (v > 255 ? kAbove255 : 0u) | (v > 256 ? kAbove256 : 0u);
+}
+
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b, uint32_t& fl) {
+    uint64_t r;
+    if (__builtin_add_overflow(a, b, &r)) {
+        fl |= kOverflow;
+        return ~0ull;
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b, uint32_t& fl) {
+    uint64_t r;
+    if (__builtin_mul_overflow(a, b, &r)) {
+        fl |= kOverflow;
+        return ~0ull;
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
+// Host side.  HIP error code reported by afmm_last_hip_error() (thread-local).
+void set_last_hip_error(int e);
+
 // Host launchers (each returns the hipError_t of its launch).
 
 // prep.hip

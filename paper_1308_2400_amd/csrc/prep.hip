@@ -110,30 +110,7 @@ hipError_t launch_transpose_f32(const float* X, int n, float* Xt, int64_t ldq, i
 }
 
 // ---------------------------------------------------------------------------
-// Counting.  Flag bits as in afmm.h.
-constexpr uint32_t kNeg = 1u, kAbove255 = 2u, kAbove256 = 4u, kOverflow = 8u;
-
-__device__ __forceinline__ uint32_t int_flags(int32_t v) {
-    return (v < 0 ? kNeg : 0u) | (v > 255 ? kAbove255 : 0u) | (v > 256 ? kAbove256 : 0u);
-}
-
-__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b, uint32_t& fl) {
-    uint64_t r;
-    if (__builtin_add_overflow(a, b, &r)) {
-        fl |= kOverflow;
-        return ~0ull;
-    }
-    return r;
-}
-
-__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b, uint32_t& fl) {
-    uint64_t r;
-    if (__builtin_mul_overflow(a, b, &r)) {
-        fl |= kOverflow;
-        return ~0ull;
-    }
-    return r;
-}
+// Counting.
 
 // Saturating sum of a uint64 over the 256 threads of a block; result in thread 0.
 __device__ uint64_t block_sum_sat(uint64_t v, uint32_t& fl) {
