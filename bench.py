@@ -33,6 +33,8 @@ def parse():
     p.add_argument("--no-split", action="store_true")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-mb", type=int, default=0,
+                   help="first run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
 
 
@@ -71,6 +73,78 @@ def cpu_baseline(w, X, Y, seconds):
             "sample": f"{k} of {w.n} rows of the same workload ({adds} additions, {dt:.1f} s)"}
 
 
+STRICT_SOURCES = ("paper_1308_2400_amd/csrc/strict_body.hpp", "paper_1308_2400_amd/csrc/strict.hip",
+                  "paper_1308_2400_amd/csrc/common.hpp")
+
+
+def strict_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STRICT_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per strict launch from the committed counter runs, if they match this kernel."""
+    path = os.path.join(ROOT, "profiles", "rep_uniform_caseB_n4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != strict_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def bench_batched(args, stream, single_issued_frac):
+    """512 products of uneven n, density and integer range: one plan, graph replays."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_1308_2400_amd as afmm
+
+    dev = torch.device("cuda:0")
+    ws = gen.batched_512()
+    log(f"bench: generating {len(ws)} batched products")
+    host = [(w.case, w.X(), w.Y()) for w in ws]
+    probs = []
+    issued = 0
+    for case, X, Y in host:
+        n = X.shape[0]
+        ints = Y if case == "A" else X
+        issued += int(np.maximum(ints, 0).astype(np.int64).sum()) * n
+        Xd = torch.from_numpy(X).to(dev)
+        Yd = torch.from_numpy(Y).to(dev)
+        probs.append((case, Xd, Yd, torch.empty((n, n), dtype=torch.float32, device=dev)))
+    plan = afmm.Plan(probs)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    ms = event_time_ms(plan.launch, args.steps, stream)
+    adds = sum(plan.problem_adds())
+    # spot parity: first row of a few products
+    ok = True
+    for t in (0, 1, len(host) // 2, len(host) - 1):
+        case, X, Y = host[t]
+        Zr, _ = oracle.strict_f32(case, X[:1], Y, rows=[0], x_rows_only=True)
+        ok &= bool(np.array_equal(probs[t][3][:1].cpu().numpy().view(np.uint32), Zr.view(np.uint32)))
+    frac = issued / (ms * 1e-3) / 1e12 / PEAK_ADD_UNPACKED
+    plan.close()
+    log(f"bench: batched {ms:.3f} ms, {adds / (ms * 1e-3):.3e} adds/s, issued frac {frac:.3f}")
+    return {"workload": "512 products, n log-uniform [32,1024], d1,d2 ~ U(0.05,1), "
+                        "integer U{0..R}, R in {3,15,63,255}, real U(-1,1)",
+            "ms": ms, "useful_adds": adds, "useful_adds_per_s": adds / (ms * 1e-3),
+            "issued_lane_adds": issued,
+            "issued_frac_of_unpacked_peak": frac,
+            "efficiency_vs_single_launch": frac / single_issued_frac,
+            "bitexact_sampled_rows": ok,
+            "timed": "whole plan launch (graph replay: prep, count, schedule, persistent kernel)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -85,6 +159,13 @@ def main():
     import paper_1308_2400_amd as afmm
 
     dev = torch.device("cuda:0")
+    if args.copy_mb:
+        src = torch.ones(args.copy_mb * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = gen.caseB_n4096(n=args.n)
     log(f"bench: generating {w.name}")
     X, Y = w.X(), w.Y()
@@ -165,7 +246,8 @@ def main():
                    "bitexact_sampled_rows": bitexact},
         "count_ms": count_ms,
         "roofline": {"bound": "alu", "achieved": strict_tflops, "peak": PEAK_ADD_TFLOPS,
-                     "unit": "TFLOP/s", "frac": strict_tflops / PEAK_ADD_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": strict_tflops / PEAK_ADD_TFLOPS,
+                     "traffic": measured_traffic(),
                      "kernel": "rep_uniform_kernel (strict, one launch = one n=4096 product)"},
     }
 
@@ -191,6 +273,9 @@ def main():
                         "strict_rel_frobenius_err_vs_f64": err_strict,
                         "speedup_over_strict": strict_ms / split_ms}
         log(f"bench: split {split_ms:.3f} ms err {err:.2e}")
+
+    if not args.no_batched:
+        out["batched"] = bench_batched(args, stream, out["strict"]["issued_frac_of_unpacked_peak"])
 
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")

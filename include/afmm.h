@@ -133,7 +133,10 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            factor's columns; case A runs on the transposed problem),
  *            1 = base-uniform (case A only: each wave walks R rows of X with
  *            the base in a scalar register; lanes over Y's columns with a
- *            per-lane count).
+ *            per-lane count),
+ *            2 = rep-uniform with base rows streamed straight into
+ *            registers (no LDS panel); falls back to 0 when the base rows
+ *            are not readable in 16-byte units (case B with n % 4 != 0).
  *   rows_per_wave R, cols_per_lane C, waves per workgroup W: one of the
  *   compiled combinations (afmm_config_supported tells which).
  */

@@ -18,6 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafmm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+# torch brings its own HIP runtime (soname libamdhip64.so.7).  Loading it first
+# makes libafmm bind to that same runtime; the other order would put two HIP
+# runtimes in one process, and device memory from one is not valid in the other.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 CASE_A, CASE_B = 0, 1

@@ -149,6 +149,7 @@ bool config_ok(afmm_case c, const afmm_config& g) {
     if (g.mapping == 0) return rep_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
     if (g.mapping == 1)
         return c == AFMM_CASE_A && base_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
+    if (g.mapping == 2) return rep_direct_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
     return false;
 }
 
@@ -211,8 +212,12 @@ afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, flo
         a.trans_out = true;
         a.q_padded = true;
     }
-    if (cfg.mapping == 0) {
-        AFMM_HIP(launch_rep_uniform(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
+    if (cfg.mapping == 2 && rep_direct_usable(a)) {
+        AFMM_HIP(launch_rep_direct(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
+    } else if (cfg.mapping == 2 || cfg.mapping == 0) {
+        // the direct variant needs float4-readable base rows; the LDS variant takes the rest
+        const afmm_config d = cfg.mapping == 0 ? cfg : builtin_config(n);
+        AFMM_HIP(launch_rep_uniform(a, d.rows_per_wave, d.cols_per_lane, d.waves, s));
     } else {
         BaseUniformArgs b{(int)n, static_cast<const float*>(X), static_cast<const int32_t*>(Y), Z};
         AFMM_HIP(launch_base_uniform(b, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));

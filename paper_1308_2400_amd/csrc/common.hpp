@@ -83,6 +83,9 @@ struct StrictArgs {
 };
 hipError_t launch_rep_uniform(const StrictArgs& a, int R, int C, int W, hipStream_t s);
 bool rep_uniform_supported(int R, int C, int W);
+hipError_t launch_rep_direct(const StrictArgs& a, int R, int C, int W, hipStream_t s);
+bool rep_direct_supported(int R, int C, int W);
+bool rep_direct_usable(const StrictArgs& a);  // Q readable in float4 units
 
 struct BaseUniformArgs {
     int n;

@@ -79,6 +79,80 @@ hipError_t launch_rep_uniform(const StrictArgs& a, int R, int C, int W, hipStrea
     return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Direct-load variant (no LDS panel; waves meet every kSyncK rows of k).
+constexpr int kSyncK = 64;
+
+template <int R, int C, int W, bool TRANS_OUT>
+__global__ __launch_bounds__(W * kWave) void rep_direct_kernel(
+    int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
+    const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
+    const float* __restrict__ Q, int64_t ldq, float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
+    const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles) {
+    constexpr int TM = W * R, TN = kWave * C;
+    const int t = xcd_remap(blockIdx.x, n_tiles);
+    const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
+    if (*esc)
+        rep_direct_tile<R, C, W, kSyncK, TRANS_OUT, true>(n_r, n_c, n_k, P8, ldp, P32, p32_sr,
+                                                          p32_sk, Q, ldq, Z, z_sr, z_sc, rb * TM,
+                                                          band * TN);
+    else
+        rep_direct_tile<R, C, W, kSyncK, TRANS_OUT, false>(n_r, n_c, n_k, P8, ldp, P32, p32_sr,
+                                                           p32_sk, Q, ldq, Z, z_sr, z_sc, rb * TM,
+                                                           band * TN);
+}
+
+template <int R, int C, int W>
+static hipError_t launch_direct(const StrictArgs& a, hipStream_t s) {
+    constexpr int TM = W * R, TN = kWave * C;
+    static_assert(TM <= kRowPad, "row padding must cover a tile");
+    const int n_row_blocks = (a.n_r + TM - 1) / TM;
+    const int n_tiles = n_row_blocks * ((a.n_c + TN - 1) / TN);
+    const bool vec = (a.ldq % 4 == 0) && (a.n_c % 4 == 0 || a.q_padded) &&
+                     (reinterpret_cast<uintptr_t>(a.Q) % 16 == 0);
+    if (!vec) return hipErrorInvalidValue;
+    dim3 grid(n_tiles), block(W * kWave);
+    if (a.trans_out)
+        hipLaunchKernelGGL((rep_direct_kernel<R, C, W, true>), grid, block, 0, s, a.n_r, a.n_c,
+                           a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z, a.z_sr,
+                           a.z_sc, a.esc, n_row_blocks, n_tiles);
+    else
+        hipLaunchKernelGGL((rep_direct_kernel<R, C, W, false>), grid, block, 0, s, a.n_r, a.n_c,
+                           a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z, a.z_sr,
+                           a.z_sc, a.esc, n_row_blocks, n_tiles);
+    return hipGetLastError();
+}
+
+#define AFMM_DIRECT_CONFIGS(X) \
+    X(8, 8, 4)                 \
+    X(8, 8, 8)                 \
+    X(6, 8, 4)                 \
+    X(4, 8, 8)                 \
+    X(8, 4, 4)                 \
+    X(16, 4, 4)                \
+    X(4, 4, 4)
+
+bool rep_direct_supported(int R, int C, int W) {
+#define AFMM_CASE(r, c, w) \
+    if (R == r && C == c && W == w) return true;
+    AFMM_DIRECT_CONFIGS(AFMM_CASE)
+#undef AFMM_CASE
+    return false;
+}
+
+bool rep_direct_usable(const StrictArgs& a) {
+    return (a.ldq % 4 == 0) && (a.n_c % 4 == 0 || a.q_padded) &&
+           (reinterpret_cast<uintptr_t>(a.Q) % 16 == 0);
+}
+
+hipError_t launch_rep_direct(const StrictArgs& a, int R, int C, int W, hipStream_t s) {
+#define AFMM_CASE(r, c, w) \
+    if (R == r && C == c && W == w) return launch_direct<r, c, w>(a, s);
+    AFMM_DIRECT_CONFIGS(AFMM_CASE)
+#undef AFMM_CASE
+    return hipErrorInvalidValue;
+}
+
 bool base_uniform_supported(int, int, int) { return false; }
 
 hipError_t launch_base_uniform(const BaseUniformArgs&, int, int, int, hipStream_t) {

@@ -102,10 +102,15 @@ __device__ __forceinline__ void rep_uniform_tile(
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;  // Z starts at +0.0
 
+    static_assert(KP == 16, "the count words of a panel are one dwordx4 per row");
     const int n_panels = (n_k + KP - 1) / KP;
     float4 stage[T::F4T];
     panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, 0, c0);
     panel_store<R, C, W, KP>(stage, lds);
+    // counts of the first panel: 16 bytes per row (scalar loads)
+    uint4 cw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) cw[r] = *reinterpret_cast<const uint4*>(prow + (int64_t)r * ldp);
     __syncthreads();
 
     for (int p = 0; p < n_panels; ++p) {
@@ -114,52 +119,60 @@ __device__ __forceinline__ void rep_uniform_tile(
         const bool more = p + 1 < n_panels;
         if (more) panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, k0 + KP, c0);
 
-#pragma unroll 1
-        for (int kq = 0; kq < KP; kq += 4) {
-            uint32_t cw[R];  // four count bytes per row, scalar loads
+        // base rows ping-pong through two register sets: row kk + 1 is read from
+        // LDS while the additions of row kk run
+        float bA[C], bB[C];
+        auto lds_row = [&](float* b, int kk) {
+            const float* brow = pan + kk * TN + lane * V;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                cw[r] = __builtin_amdgcn_readfirstlane(
-                    *reinterpret_cast<const uint32_t*>(prow + (int64_t)r * ldp + k0 + kq));
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                float b[C];
-                const float* brow = pan + (kq + kk) * TN + lane * V;
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    if constexpr (V == 4) {
-                        const float4 t = *reinterpret_cast<const float4*>(brow + g * kWave * V);
-                        b[g * 4 + 0] = t.x;
-                        b[g * 4 + 1] = t.y;
-                        b[g * 4 + 2] = t.z;
-                        b[g * 4 + 3] = t.w;
-                    } else if constexpr (V == 2) {
-                        const float2 t = *reinterpret_cast<const float2*>(brow + g * kWave * V);
-                        b[g * 2 + 0] = t.x;
-                        b[g * 2 + 1] = t.y;
-                    } else {
-                        b[g] = brow[g * kWave];
-                    }
+            for (int g = 0; g < G; ++g) {
+                if constexpr (V == 4) {
+                    const float4 t = *reinterpret_cast<const float4*>(brow + g * kWave * V);
+                    b[g * 4 + 0] = t.x;
+                    b[g * 4 + 1] = t.y;
+                    b[g * 4 + 2] = t.z;
+                    b[g * 4 + 3] = t.w;
+                } else if constexpr (V == 2) {
+                    const float2 t = *reinterpret_cast<const float2*>(brow + g * kWave * V);
+                    b[g * 2 + 0] = t.x;
+                    b[g * 2 + 1] = t.y;
+                } else {
+                    b[g] = brow[g * kWave];
                 }
+            }
+        };
+        lds_row(bA, 0);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    uint32_t rep = (cw[r] >> (8 * kk)) & 0xFFu;
-                    if (rep != 0) {  // a zero Rep-factor adds nothing
-                        if (ESC && rep == 0xFFu) {
-                            const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr +
-                                                     (int64_t)(k0 + kq + kk) * p32_sk];
-                            rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
-                        }
-                        do {
+        for (int kk = 0; kk < KP; ++kk) {
+            float* b = (kk & 1) ? bB : bA;
+            if (kk + 1 < KP) lds_row((kk & 1) ? bA : bB, kk + 1);
 #pragma unroll
-                            for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
-                        } while (--rep != 0);
+            for (int r = 0; r < R; ++r) {
+                const uint32_t word = (kk >> 2) == 0 ? cw[r].x
+                                    : (kk >> 2) == 1 ? cw[r].y
+                                    : (kk >> 2) == 2 ? cw[r].z : cw[r].w;
+                uint32_t rep = (__builtin_amdgcn_readfirstlane(word) >> (8 * (kk & 3))) & 0xFFu;
+                if (rep != 0) {  // a zero Rep-factor adds nothing
+                    if (ESC && rep == 0xFFu) {
+                        const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr +
+                                                 (int64_t)(k0 + kk) * p32_sk];
+                        rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
                     }
+                    do {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+                    } while (--rep != 0);
                 }
             }
         }
 
-        if (more) panel_store<R, C, W, KP>(stage, lds + ((p + 1) & 1) * (KP * TN));
+        if (more) {
+            // counts of the next panel (the current ones are spent), then its base rows
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                cw[r] = *reinterpret_cast<const uint4*>(prow + (int64_t)r * ldp + k0 + KP);
+            panel_store<R, C, W, KP>(stage, lds + ((p + 1) & 1) * (KP * TN));
+        }
         __syncthreads();
     }
 
@@ -178,6 +191,131 @@ __device__ __forceinline__ void rep_uniform_tile(
                         Z[(int64_t)col * z_sc + row] = acc[r][g * V + v];
                     else
                         Z[(int64_t)row * z_sr + col] = acc[r][g * V + v];
+                }
+            }
+    }
+}
+
+}  // namespace afmm
+
+namespace afmm {
+
+// ---------------------------------------------------------------------------
+// Direct-load variant of the count-uniform tile: no LDS panel and no
+// per-panel barrier.  The W waves of a block own different rows but the same
+// 64*C columns, so each base row they read is shared through the compute
+// unit's L1; each wave streams its base rows straight into registers, four k
+// ahead (two register sets, ping-pong, no copies), and the waves only meet at
+// a barrier every SYNC_K rows of k, which bounds how far apart they drift.
+// Requires C % 4 == 0 and rows of Q readable in float4 units.
+template <int C>
+struct DirectBuf {
+    float4 v[4][C / 4];
+};
+
+template <int C>
+__device__ __forceinline__ void direct_load(DirectBuf<C>& d, const float* __restrict__ Q,
+                                            int64_t ldq, int n_k, int k0, const int* colo,
+                                            const bool* cok) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int k = k0 + kk;
+#pragma unroll
+        for (int g = 0; g < C / 4; ++g) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k < n_k && cok[g]) v = *reinterpret_cast<const float4*>(Q + (int64_t)k * ldq + colo[g]);
+            d.v[kk][g] = v;
+        }
+    }
+}
+
+template <int R, int C, bool ESC>
+__device__ __forceinline__ void direct_group(float (&acc)[R][C], const DirectBuf<C>& d,
+                                             const uint8_t* __restrict__ prow, int64_t ldp,
+                                             const int32_t* __restrict__ P32, int64_t p32_sr,
+                                             int64_t p32_sk, int rw0, int k0) {
+    uint32_t cw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        cw[r] = __builtin_amdgcn_readfirstlane(
+            *reinterpret_cast<const uint32_t*>(prow + (int64_t)r * ldp + k0));
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        float b[C];
+#pragma unroll
+        for (int g = 0; g < C / 4; ++g) {
+            b[4 * g + 0] = d.v[kk][g].x;
+            b[4 * g + 1] = d.v[kk][g].y;
+            b[4 * g + 2] = d.v[kk][g].z;
+            b[4 * g + 3] = d.v[kk][g].w;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            uint32_t rep = (cw[r] >> (8 * kk)) & 0xFFu;
+            if (rep != 0) {
+                if (ESC && rep == 0xFFu) {
+                    const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr + (int64_t)(k0 + kk) * p32_sk];
+                    rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
+                }
+                do {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+                } while (--rep != 0);
+            }
+        }
+    }
+}
+
+template <int R, int C, int W, int SYNC_K, bool TRANS_OUT, bool ESC>
+__device__ __forceinline__ void rep_direct_tile(
+    int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
+    const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
+    const float* __restrict__ Q, int64_t ldq, float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
+    int r0, int c0) {
+    static_assert(C % 4 == 0, "direct tiles read float4 columns");
+    static_assert(SYNC_K % 8 == 0, "barrier spacing is a multiple of two groups");
+    constexpr int G = C / 4;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int rw0 = r0 + wave * R;
+    const uint8_t* __restrict__ prow = P8 + (int64_t)rw0 * ldp;
+    int colo[G];
+    bool cok[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        colo[g] = c0 + g * kWave * 4 + lane * 4;
+        cok[g] = colo[g] < n_c;
+    }
+    float acc[R][C];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;  // Z starts at +0.0
+
+    DirectBuf<C> ba, bb;
+    direct_load<C>(ba, Q, ldq, n_k, 0, colo, cok);
+    for (int k0 = 0; k0 < n_k; k0 += 8) {
+        direct_load<C>(bb, Q, ldq, n_k, k0 + 4, colo, cok);
+        direct_group<R, C, ESC>(acc, ba, prow, ldp, P32, p32_sr, p32_sk, rw0, k0);
+        if (k0 + 8 < n_k) direct_load<C>(ba, Q, ldq, n_k, k0 + 8, colo, cok);
+        if (k0 + 4 < n_k) direct_group<R, C, ESC>(acc, bb, prow, ldp, P32, p32_sr, p32_sk, rw0, k0 + 4);
+        if ((k0 + 8) % SYNC_K == 0) __syncthreads();
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = rw0 + r;
+        if (row >= n_r) break;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = colo[g] + v;
+                if (col < n_c) {
+                    if (TRANS_OUT)
+                        Z[(int64_t)col * z_sc + row] = acc[r][4 * g + v];
+                    else
+                        Z[(int64_t)row * z_sr + col] = acc[r][4 * g + v];
                 }
             }
     }

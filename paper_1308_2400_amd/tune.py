@@ -1,0 +1,118 @@
+"""Autotuner for the strict path: times every compiled kernel configuration on
+representative inputs and writes the fastest per (case, size) to a tuning table.
+
+    python -m paper_1308_2400_amd.tune [--out tune_cache.json] [--quick]
+
+Every configuration's output is compared bit for bit with the first one's: all
+of them perform the same additions in the same order, so any difference is a
+bug.  The table is loaded by the package at import (AFMM_TUNE_CACHE overrides
+the path) and handed to the library with afmm_set_tuning.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(_HERE)
+
+CANDIDATES = [(m, r, c, w) for m in (0, 2) for r in (2, 4, 6, 8, 16) for c in (1, 2, 4, 8)
+              for w in (4, 8)]
+
+
+def _inputs(case, n, seed):
+    """Inputs with the shape of the reference workloads (generator of the test suite)."""
+    sys.path.insert(0, ROOT)
+    import gen
+    if case == "B":
+        w = gen.caseB_n4096(n=n)
+    elif n <= 512:
+        w = gen.Workload(f"tuneA_{n}", "A", n, gen.RealSpec(gen.UNIFORM01, 0.5),
+                         gen.IntSpec(gen.INT_UNIFORM, 0.8, 1, 9), seed)
+    else:
+        w = gen.caseA_n16384(n=n)
+    return w.X(), w.Y()
+
+
+def time_config(afmm, case, Xd, Yd, Z, cfg, reps, ws):
+    import torch
+    afmm.multiply(case, Xd, Yd, out=Z, config=cfg, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        afmm.multiply(case, Xd, Yd, out=Z, config=cfg, workspace=ws)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(sizes, reps=3, log=print):
+    import torch
+    import paper_1308_2400_amd as afmm
+    afmm.set_tuning([])  # time the built-in rule, not a previous table
+    results = []
+    for case, n in sizes:
+        X, Y = _inputs(case, n, 99)
+        Xd = torch.from_numpy(X).cuda()
+        Yd = torch.from_numpy(Y).cuda()
+        ws = torch.empty(afmm.workspace_size(case, n), dtype=torch.uint8, device="cuda")
+        ref = None
+        timings = []
+        for cfg in CANDIDATES:
+            if not afmm.config_supported(case, cfg):
+                continue
+            Z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            ms = time_config(afmm, case, Xd, Yd, Z, cfg, reps, ws)
+            if ref is None:
+                ref = Z.clone()
+            elif not torch.equal(ref.view(torch.int32), Z.view(torch.int32)):
+                raise RuntimeError(f"config {cfg} differs from {timings[0][1]} at case {case} n={n}")
+            timings.append((ms, cfg))
+            log(f"tune case {case} n={n} cfg={cfg}: {ms:.4f} ms")
+        timings.sort()
+        best_ms, best = timings[0]
+        results.append({"case": case, "n": n, "config": list(best), "ms": best_ms,
+                        "default": list(afmm.default_config(case, n)),
+                        "all": [[list(c), m] for m, c in timings]})
+        log(f"tune case {case} n={n}: best {best} {best_ms:.4f} ms")
+    return results
+
+
+def to_table(results):
+    """Size ranges: each tuned size covers up to the geometric midpoint to its neighbours."""
+    entries = []
+    for case in ("A", "B"):
+        rs = sorted((r for r in results if r["case"] == case), key=lambda r: r["n"])
+        for i, r in enumerate(rs):
+            lo = 1 if i == 0 else int((rs[i - 1]["n"] * r["n"]) ** 0.5) + 1
+            hi = 1 << 30 if i == len(rs) - 1 else int((r["n"] * rs[i + 1]["n"]) ** 0.5)
+            entries.append({"case": case, "n_lo": lo, "n_hi": hi, "config": r["config"],
+                            "tuned_at": r["n"], "ms": r["ms"]})
+    return entries
+
+
+def main():
+    p = argparse.ArgumentParser()
+    p.add_argument("--out", default=os.path.join(_HERE, "tune_cache.json"))
+    p.add_argument("--quick", action="store_true")
+    a = p.parse_args()
+    if a.quick:
+        sizes = [("B", 1024), ("B", 4096), ("A", 1024), ("A", 4096)]
+    else:
+        sizes = [("B", 256), ("B", 1024), ("B", 2048), ("B", 4096), ("B", 8192),
+                 ("A", 256), ("A", 1024), ("A", 2048), ("A", 4096), ("A", 8192)]
+    t = time.time()
+    results = tune(sizes, log=lambda m: print(m, flush=True))
+    out = {"generated_by": "python -m paper_1308_2400_amd.tune", "seconds": time.time() - t,
+           "entries": to_table(results), "results": results}
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"wrote {a.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

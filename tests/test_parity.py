@@ -73,7 +73,9 @@ def test_strict_bitexact_sizes(dev, case, n):
 
 
 CONFIGS = [(0, 8, 8, 8), (0, 4, 8, 8), (0, 8, 4, 8), (0, 4, 4, 8), (0, 8, 8, 4), (0, 8, 4, 4),
-           (0, 4, 4, 4), (0, 4, 2, 4), (0, 2, 1, 4)]
+           (0, 4, 4, 4), (0, 4, 2, 4), (0, 2, 1, 4),
+           (2, 8, 8, 4), (2, 8, 8, 8), (2, 6, 8, 4), (2, 4, 8, 8), (2, 8, 4, 4), (2, 16, 4, 4),
+           (2, 4, 4, 4)]
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
@@ -92,7 +94,17 @@ def test_caseA_n256_full(dev):
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
-def test_strict_large_counts_escape(dev, case):
+@pytest.mark.parametrize("n", [130, 257, 1000])
+def test_direct_variant_sizes(dev, case, n):
+    """The direct-load variant; n % 4 != 0 in case B falls back to the LDS variant."""
+    X, Y = _rand_case(case, n, 300 + n, int_hi=6)
+    for cfg in [(2, 8, 8, 4), (2, 16, 4, 4)]:
+        _check_strict(dev, case, X, Y, config=cfg)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("cfg", [(0, 8, 8, 8), (2, 8, 8, 4)], ids=str)
+def test_strict_large_counts_escape(dev, case, cfg):
     """Counts at and above 255 take the escape path (full int32 re-read)."""
     n = 150
     r = np.random.default_rng(5)
@@ -102,7 +114,7 @@ def test_strict_large_counts_escape(dev, case):
     ints[pos] = r.integers(250, 700, pos.sum())
     ints[0, 0] = 255
     ints[1, 1] = 254
-    _check_strict(dev, case, X, Y)
+    _check_strict(dev, case, X, Y, config=cfg)
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
