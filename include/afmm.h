@@ -137,14 +137,18 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            2 = rep-uniform with base rows streamed straight into
  *            registers (no LDS panel); falls back to 0 when the base rows
  *            are not readable in 16-byte units (case B with n % 4 != 0).
- *   rows_per_wave R, cols_per_lane C, waves per workgroup W: one of the
- *   compiled combinations (afmm_config_supported tells which).
+ *   rows_per_wave R, cols_per_lane C, waves per workgroup W, unroll U (1
+ *   or 2: the repetition loop does U additions per trip; 0 means 1),
+ *   k_panel (rows of the base staged per LDS panel, 8 or 16; 0 means 16):
+ *   one of the compiled combinations (afmm_config_supported tells which).
  */
 typedef struct {
     int32_t mapping;
     int32_t rows_per_wave;
     int32_t cols_per_lane;
     int32_t waves;
+    int32_t unroll;
+    int32_t k_panel;
 } afmm_config;
 
 /* 1 when `cfg` names a compiled kernel for case c, else 0. */

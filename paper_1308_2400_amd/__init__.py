@@ -36,10 +36,12 @@ STATUS = {0: "AFMM_OK", 1: "AFMM_ERR_INVALID_ARG", 2: "AFMM_ERR_ALIAS",
 
 class afmm_config(ctypes.Structure):
     _fields_ = [("mapping", ctypes.c_int32), ("rows_per_wave", ctypes.c_int32),
-                ("cols_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("k_panel", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.mapping, self.rows_per_wave, self.cols_per_lane, self.waves)
+        return (self.mapping, self.rows_per_wave, self.cols_per_lane, self.waves,
+                self.unroll or 1, self.k_panel or 16)
 
 
 class afmm_problem(ctypes.Structure):
@@ -151,7 +153,7 @@ def multiply(case, X, Y, mode="strict", out=None, workspace=None, config=None):
     if config is not None:
         if m != MODE_STRICT:
             raise ValueError("an explicit config applies to the strict mode only")
-        cfg = config if isinstance(config, afmm_config) else afmm_config(*config)
+        cfg = _cfg(config)
         st = _lib.afmm_multiply_strict_config(c, n, X.data_ptr(), Y.data_ptr(), Z.data_ptr(),
                                               ctypes.byref(cfg), ws, wsb, _stream())
     else:
@@ -195,22 +197,26 @@ def validate(case, X, Y, mode="strict") -> int:
 
 
 def default_config(case, n):
+    """(mapping, R, C, W, unroll) the library uses for a strict product of this size."""
     return _lib.afmm_default_config(_case_id(case), n).as_tuple()
 
 
+def _cfg(cfg):
+    return cfg if isinstance(cfg, afmm_config) else afmm_config(*cfg)
+
+
 def config_supported(case, cfg) -> bool:
-    c = cfg if isinstance(cfg, afmm_config) else afmm_config(*cfg)
-    return bool(_lib.afmm_config_supported(_case_id(case), ctypes.byref(c)))
+    return bool(_lib.afmm_config_supported(_case_id(case), ctypes.byref(_cfg(cfg))))
 
 
 def set_tuning(entries):
-    """entries: iterable of (case, n_lo, n_hi, (mapping, R, C, W))."""
+    """entries: iterable of (case, n_lo, n_hi, (mapping, R, C, W[, unroll]))."""
     entries = list(entries)
     k = len(entries)
     cases = (ctypes.c_int32 * max(k, 1))(*[_case_id(e[0]) for e in entries])
     lo = (ctypes.c_int64 * max(k, 1))(*[e[1] for e in entries])
     hi = (ctypes.c_int64 * max(k, 1))(*[e[2] for e in entries])
-    cfgs = (afmm_config * max(k, 1))(*[afmm_config(*e[3]) for e in entries])
+    cfgs = (afmm_config * max(k, 1))(*[_cfg(e[3]) for e in entries])
     _check("set_tuning", _lib.afmm_set_tuning(k, cases, lo, hi, cfgs))
 
 

@@ -146,7 +146,12 @@ std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
 
 bool config_ok(afmm_case c, const afmm_config& g) {
-    if (g.mapping == 0) return rep_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
+    const int u = g.unroll == 0 ? 1 : g.unroll;
+    const int kp = g.k_panel == 0 ? 16 : g.k_panel;
+    if (g.mapping == 0)
+        return rep_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
+    if (kp != 16) return false;
+    if (u != 1) return false;
     if (g.mapping == 1)
         return c == AFMM_CASE_A && base_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
     if (g.mapping == 2) return rep_direct_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
@@ -161,11 +166,11 @@ afmm_config builtin_config(int64_t n) {
     for (const auto& k : cand) {
         const int64_t tm = (int64_t)k[0] * k[2], tn = 64LL * k[1];
         const int64_t tiles = ((n + tm - 1) / tm) * ((n + tn - 1) / tn);
-        if (tiles >= 512 && n >= tn / 2) return afmm_config{0, k[0], k[1], k[2]};
+        if (tiles >= 512 && n >= tn / 2) return afmm_config{0, k[0], k[1], k[2], 1, 16};
     }
-    if (n >= 256) return afmm_config{0, 4, 4, 4};
-    if (n >= 128) return afmm_config{0, 4, 2, 4};
-    return afmm_config{0, 2, 1, 4};
+    if (n >= 256) return afmm_config{0, 4, 4, 4, 1, 16};
+    if (n >= 128) return afmm_config{0, 4, 2, 4, 1, 16};
+    return afmm_config{0, 2, 1, 4, 1, 16};
 }
 
 afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
@@ -217,7 +222,9 @@ afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, flo
     } else if (cfg.mapping == 2 || cfg.mapping == 0) {
         // the direct variant needs float4-readable base rows; the LDS variant takes the rest
         const afmm_config d = cfg.mapping == 0 ? cfg : builtin_config(n);
-        AFMM_HIP(launch_rep_uniform(a, d.rows_per_wave, d.cols_per_lane, d.waves, s));
+        AFMM_HIP(launch_rep_uniform(a, d.rows_per_wave, d.cols_per_lane, d.waves,
+                                    d.unroll == 0 ? 1 : d.unroll,
+                                    d.k_panel == 0 ? 16 : d.k_panel, s));
     } else {
         BaseUniformArgs b{(int)n, static_cast<const float*>(X), static_cast<const int32_t*>(Y), Z};
         AFMM_HIP(launch_base_uniform(b, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));

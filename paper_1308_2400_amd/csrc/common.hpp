@@ -81,8 +81,9 @@ struct StrictArgs {
     bool trans_out;                          // z_sr == 1: output (r, c) at c*z_sc + r
     bool q_padded;                           // Q rows readable up to round_up(n_c, 4)
 };
-hipError_t launch_rep_uniform(const StrictArgs& a, int R, int C, int W, hipStream_t s);
-bool rep_uniform_supported(int R, int C, int W);
+hipError_t launch_rep_uniform(const StrictArgs& a, int R, int C, int W, int U, int KP,
+                              hipStream_t s);
+bool rep_uniform_supported(int R, int C, int W, int U, int KP);
 hipError_t launch_rep_direct(const StrictArgs& a, int R, int C, int W, hipStream_t s);
 bool rep_direct_supported(int R, int C, int W);
 bool rep_direct_usable(const StrictArgs& a);  // Q readable in float4 units

@@ -37,6 +37,24 @@ struct RepTile {
     static_assert(TM <= kRowPad, "row padding must cover a tile");
 };
 
+// The count bytes of one row for one panel: KP bytes, one scalar load.
+template <int KP>
+struct PanelCounts;
+template <>
+struct PanelCounts<16> {
+    uint4 v;
+    __device__ __forceinline__ void load(const uint8_t* p) { v = *reinterpret_cast<const uint4*>(p); }
+    __device__ __forceinline__ uint32_t get(int i) const {
+        return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+    }
+};
+template <>
+struct PanelCounts<8> {
+    uint2 v;
+    __device__ __forceinline__ void load(const uint8_t* p) { v = *reinterpret_cast<const uint2*>(p); }
+    __device__ __forceinline__ uint32_t get(int i) const { return i == 0 ? v.x : v.y; }
+};
+
 // Stage panel rows [k0, k0 + KP) x columns [c0, c0 + TN) of the base into
 // registers (float4 units; out-of-range entries read as zero).
 template <int R, int C, int W, int KP, bool VEC>
@@ -68,6 +86,29 @@ __device__ __forceinline__ void panel_load(float4* buf,
     }
 }
 
+// Same with a buffer resource covering the base rows from k0 on: the
+// per-thread offsets are fixed, the panel start moves in scalar registers, and
+// rows past the end (or bytes past num_records) read as zero instead of
+// faulting.  Columns past n_c read neighbouring data; those lanes are never
+// stored, and rows past n_k have zero counts, so neither value is used.
+template <int R, int C, int W, int KP>
+__device__ __forceinline__ void panel_load_buf(float4* buf, const float* __restrict__ Q,
+                                               int64_t ldq, int n_k, int k0,
+                                               const uint32_t* voff) {
+    using T = RepTile<R, C, W, KP>;
+    const int rows = n_k - k0 > 0 ? n_k - k0 : 0;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(Q + (int64_t)k0 * ldq), (short)0, (int)(rows * ldq * 4), 0x00020000);
+#pragma unroll
+    for (int s = 0; s < T::F4T; ++s) {
+        const int e = threadIdx.x + s * W * kWave;
+        if (T::F4 % (W * kWave) == 0 || e < T::F4)
+            buf[s] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff[s], 0, 0));
+        else
+            buf[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
 template <int R, int C, int W, int KP>
 __device__ __forceinline__ void panel_store(const float4* buf,
                                             float* lds) {
@@ -83,7 +124,10 @@ __device__ __forceinline__ void panel_store(const float4* buf,
 // LDS_FLOATS floats.  All threads of the block must call it (barriers).
 // ESC: some count byte may be 255, meaning "re-read the full int32 count";
 // without it the byte is the count (the packing pass reports which holds).
-template <int R, int C, int W, int KP, bool VEC, bool TRANS_OUT, bool ESC>
+// VEC: float4 loads allowed; BUF (with VEC): buffer-resource loads (the base
+// matrix is below 2^31 bytes).  UNR: repetition loop unrolled by two.
+template <int R, int C, int W, int KP, bool VEC, bool TRANS_OUT, bool ESC, bool BUF = false,
+          int UNR = 1>
 __device__ __forceinline__ void rep_uniform_tile(
     int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
     const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
@@ -102,22 +146,32 @@ __device__ __forceinline__ void rep_uniform_tile(
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;  // Z starts at +0.0
 
-    static_assert(KP == 16, "the count words of a panel are one dwordx4 per row");
+    static_assert(KP == 16 || KP == 8, "the count words of a panel are one dwordx4 / dwordx2 per row");
     const int n_panels = (n_k + KP - 1) / KP;
     float4 stage[T::F4T];
-    panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, 0, c0);
+    uint32_t voff[T::F4T];
+#pragma unroll
+    for (int s = 0; s < T::F4T; ++s) {
+        const int e = threadIdx.x + s * W * kWave;
+        voff[s] = (uint32_t)(((e / (TN / 4)) * ldq + c0 + (e % (TN / 4)) * 4) * 4);
+    }
+    if (BUF) panel_load_buf<R, C, W, KP>(stage, Q, ldq, n_k, 0, voff);
+    else panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, 0, c0);
     panel_store<R, C, W, KP>(stage, lds);
     // counts of the first panel: 16 bytes per row (scalar loads)
-    uint4 cw[R];
+    PanelCounts<KP> cw[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) cw[r] = *reinterpret_cast<const uint4*>(prow + (int64_t)r * ldp);
+    for (int r = 0; r < R; ++r) cw[r].load(prow + (int64_t)r * ldp);
     __syncthreads();
 
     for (int p = 0; p < n_panels; ++p) {
         const int k0 = p * KP;
         const float* pan = lds + (p & 1) * (KP * TN);
         const bool more = p + 1 < n_panels;
-        if (more) panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, k0 + KP, c0);
+        if (more) {
+            if (BUF) panel_load_buf<R, C, W, KP>(stage, Q, ldq, n_k, k0 + KP, voff);
+            else panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, k0 + KP, c0);
+        }
 
         // base rows ping-pong through two register sets: row kk + 1 is read from
         // LDS while the additions of row kk run
@@ -148,9 +202,7 @@ __device__ __forceinline__ void rep_uniform_tile(
             if (kk + 1 < KP) lds_row((kk & 1) ? bA : bB, kk + 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const uint32_t word = (kk >> 2) == 0 ? cw[r].x
-                                    : (kk >> 2) == 1 ? cw[r].y
-                                    : (kk >> 2) == 2 ? cw[r].z : cw[r].w;
+                const uint32_t word = cw[r].get(kk >> 2);
                 uint32_t rep = (__builtin_amdgcn_readfirstlane(word) >> (8 * (kk & 3))) & 0xFFu;
                 if (rep != 0) {  // a zero Rep-factor adds nothing
                     if (ESC && rep == 0xFFu) {
@@ -158,10 +210,24 @@ __device__ __forceinline__ void rep_uniform_tile(
                                                  (int64_t)(k0 + kk) * p32_sk];
                         rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
                     }
-                    do {
+                    if (UNR == 2) {
+                        // the same base added rep times: an odd one first, then pairs
+                        if (rep & 1u) {
 #pragma unroll
-                        for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
-                    } while (--rep != 0);
+                            for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+                        }
+                        for (rep >>= 1; rep != 0; --rep) {
+#pragma unroll
+                            for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+#pragma unroll
+                            for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+                        }
+                    } else {
+                        do {
+#pragma unroll
+                            for (int c = 0; c < C; ++c) acc[r][c] = acc[r][c] + b[c];
+                        } while (--rep != 0);
+                    }
                 }
             }
         }
@@ -170,7 +236,7 @@ __device__ __forceinline__ void rep_uniform_tile(
             // counts of the next panel (the current ones are spent), then its base rows
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                cw[r] = *reinterpret_cast<const uint4*>(prow + (int64_t)r * ldp + k0 + KP);
+                cw[r].load(prow + (int64_t)r * ldp + k0 + KP);
             panel_store<R, C, W, KP>(stage, lds + ((p + 1) & 1) * (KP * TN));
         }
         __syncthreads();

@@ -81,14 +81,20 @@ def test_config_table(afmm):
     assert not afmm.config_supported("B", (1, 8, 8, 8))  # base-uniform is case A only
     for n in (1, 100, 256, 2048, 4096, 16384):
         assert afmm.config_supported("B", afmm.default_config("B", n))
+    assert afmm.config_supported("B", (0, 8, 8, 8, 2))
+    assert not afmm.config_supported("B", (2, 8, 8, 4, 2))  # unroll 2 only in the LDS kernel
+    afmm.set_tuning([])
+    builtin = afmm.default_config("B", 4096)
     afmm.set_tuning([("B", 1000, 5000, (0, 4, 4, 4))])
-    assert afmm.default_config("B", 4096) == (0, 4, 4, 4)
-    assert afmm.default_config("A", 4096) != (0, 4, 4, 4) or True
+    assert afmm.default_config("B", 4096) == (0, 4, 4, 4, 1, 16)
+    assert afmm.default_config("B", 999) != (0, 4, 4, 4, 1) or builtin == (0, 4, 4, 4, 1, 16)
+    assert afmm.default_config("A", 4096) == afmm.default_config("A", 4096)
     with pytest.raises(afmm.AfmmError):
         afmm.set_tuning([("B", 1, 2, (0, 3, 3, 3))])
-    assert afmm.default_config("B", 4096) == (0, 4, 4, 4)  # rejected table left it unchanged
+    assert afmm.default_config("B", 4096) == (0, 4, 4, 4, 1, 16)  # rejected table left it unchanged
     afmm.set_tuning([])
-    assert afmm.default_config("B", 4096) != (0, 4, 4, 4) or afmm.default_config("B", 4096)
+    assert afmm.default_config("B", 4096) == builtin
+    afmm.load_tuning()
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
