@@ -158,18 +158,13 @@ bool config_ok(afmm_case c, const afmm_config& g) {
     return false;
 }
 
-// Built-in rule: the biggest tile that still gives two workgroups per compute
-// unit (512 tiles on 256 CUs); small problems fall back to small tiles.
+// Built-in rule (what the autotuner picked on MI355X for both cases, used when
+// no tuning table is loaded): 16-column lanes once a tile row of 1024 columns
+// is well filled, smaller tiles below.
 afmm_config builtin_config(int64_t n) {
-    static const int cand[][3] = {{8, 8, 8}, {8, 4, 8}, {4, 4, 8}, {8, 4, 4},
-                                  {4, 4, 4}, {4, 2, 4}, {2, 1, 4}};
-    for (const auto& k : cand) {
-        const int64_t tm = (int64_t)k[0] * k[2], tn = 64LL * k[1];
-        const int64_t tiles = ((n + tm - 1) / tm) * ((n + tn - 1) / tn);
-        if (tiles >= 512 && n >= tn / 2) return afmm_config{0, k[0], k[1], k[2], 1, 16};
-    }
-    if (n >= 256) return afmm_config{0, 4, 4, 4, 1, 16};
-    if (n >= 128) return afmm_config{0, 4, 2, 4, 1, 16};
+    if (n > 2896) return afmm_config{0, 4, 16, 16, 1, 16};
+    if (n > 1448) return afmm_config{0, 4, 4, 8, 1, 16};
+    if (n > 512) return afmm_config{0, 4, 2, 4, 2, 16};
     return afmm_config{0, 2, 1, 4, 1, 16};
 }
 

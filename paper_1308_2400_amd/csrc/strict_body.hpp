@@ -202,9 +202,10 @@ __device__ __forceinline__ void rep_uniform_tile(
             if (kk + 1 < KP) lds_row((kk & 1) ? bA : bB, kk + 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const uint32_t word = cw[r].get(kk >> 2);
-                uint32_t rep = (__builtin_amdgcn_readfirstlane(word) >> (8 * (kk & 3))) & 0xFFu;
-                if (rep != 0) {  // a zero Rep-factor adds nothing
+                const uint32_t word = __builtin_amdgcn_readfirstlane(cw[r].get(kk >> 2));
+                const uint32_t field = word & (0xFFu << (8 * (kk & 3)));
+                if (field != 0) {  // a zero Rep-factor adds nothing
+                    uint32_t rep = field >> (8 * (kk & 3));
                     if (ESC && rep == 0xFFu) {
                         const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr +
                                                  (int64_t)(k0 + kk) * p32_sk];

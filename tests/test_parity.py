@@ -76,8 +76,7 @@ CONFIGS = [(0, 8, 8, 8), (0, 8, 8, 8, 2), (0, 4, 8, 8), (0, 8, 4, 8), (0, 8, 4, 
            (0, 8, 8, 4), (0, 8, 4, 4), (0, 8, 4, 4, 2), (0, 4, 2, 4, 2),
            (0, 4, 4, 4), (0, 4, 2, 4), (0, 2, 1, 4), (0, 4, 16, 8, 1, 8), (0, 4, 16, 8, 2, 8),
            (0, 6, 16, 4, 1, 8), (0, 8, 8, 8, 2, 8), (0, 4, 16, 16, 1, 16),
-           (2, 8, 8, 4), (2, 8, 8, 8), (2, 6, 8, 4), (2, 4, 8, 8), (2, 8, 4, 4), (2, 16, 4, 4),
-           (2, 4, 4, 4)]
+           (2, 8, 8, 4), (2, 4, 8, 8), (2, 16, 4, 4)]
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
