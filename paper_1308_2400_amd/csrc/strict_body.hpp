@@ -244,22 +244,33 @@ __device__ __forceinline__ void rep_uniform_tile(
     }
 
     // Store: column of acc[r][g*V + v] is c0 + g*64*V + lane*V + v.
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int row = rw0 + r;
-        if (row >= n_r) break;
+    if (TRANS_OUT) {
+        // the R rows of one column are consecutive in Z (z_sr == 1)
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int col = c0 + g * kWave * V + lane * V + v;
                 if (col < n_c) {
-                    if (TRANS_OUT)
-                        Z[(int64_t)col * z_sc + row] = acc[r][g * V + v];
-                    else
-                        Z[(int64_t)row * z_sr + col] = acc[r][g * V + v];
+                    float* zp = Z + (int64_t)col * z_sc + rw0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (rw0 + r < n_r) zp[r] = acc[r][g * V + v];
                 }
             }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = rw0 + r;
+            if (row >= n_r) break;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int col = c0 + g * kWave * V + lane * V + v;
+                    if (col < n_c) Z[(int64_t)row * z_sr + col] = acc[r][g * V + v];
+                }
+        }
     }
 }
 
