@@ -33,6 +33,8 @@ def parse():
     p.add_argument("--no-split", action="store_true")
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--table1", action="store_true",
+                   help="run the paper's Table 1 parameter grid (case A) instead of the benchmark")
     p.add_argument("--copy-mb", type=int, default=0,
                    help="first run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -145,6 +147,57 @@ def bench_batched(args, stream, single_issued_frac):
             "timed": "whole plan launch (graph replay: prep, count, schedule, persistent kernel)"}
 
 
+TABLE1_N = (250, 500, 750, 1000, 1250, 1500, 1750, 2000)
+TABLE1_MU = (1, 3, 5, 7, 14, 21)
+# the paper's Table 1 times (seconds, Pentium 1.6 GHz, single thread) for context
+TABLE1_PAPER_2000 = {"ikj": 147.078, 1: 53.375, 3: 94.6875, 5: 120.8515, 7: 145.8985,
+                     14: 119.516, 21: 122.491}
+
+
+def table1(args):
+    """Section 2.3.1 / Table 1 grid: case A, d1 = 1/3, d2 = 1/2 for mu' <= 7 and 1/5, 2/5
+    for 14 and 21.  The distribution of Y's non-zeros is not stated; both readings are run:
+    every non-zero equal to mu', and Uniform{1..2mu'-1} (mean mu')."""
+    import torch
+
+    import gen
+    import oracle
+    import paper_1308_2400_amd as afmm
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in TABLE1_N:
+        for mu in TABLE1_MU:
+            d1, d2 = (1 / 3, 1 / 2) if mu <= 7 else (1 / 5, 2 / 5)
+            for ydist in ("const", "uniform"):
+                ispec = (gen.IntSpec(gen.INT_UNIFORM, d2, mu, mu) if ydist == "const"
+                         else gen.IntSpec(gen.INT_UNIFORM, d2, 1, 2 * mu - 1))
+                w = gen.Workload(f"table1_n{n}_mu{mu}_{ydist}", "A", n,
+                                 gen.RealSpec(gen.UNIFORM01, d1), ispec, gen.SEED0 + 6,
+                                 100 * mu + (1 if ydist == "uniform" else 0))
+                X, Y = w.X(), w.Y()
+                Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+                Z = afmm.multiply("A", Xd, Yd)
+                adds = afmm.count_adds("A", Xd, Yd)
+                ms = event_time_ms(lambda: afmm.multiply("A", Xd, Yd, out=Z), max(args.steps, 3),
+                                   stream)
+                r = {"n": n, "mu_prime": mu, "d1": d1, "d2": d2, "y_nonzeros": ydist,
+                     "adds": adds, "expected_adds": w.expected_adds(), "gpu_ms": ms,
+                     "adds_per_s": adds / (ms * 1e-3)}
+                if n == 250:  # the oracle (single thread) for the smallest size, bit for bit
+                    t = time.perf_counter()
+                    Zr, a2 = oracle.caseA_f32(X, Y)
+                    r["cpu_oracle_s"] = time.perf_counter() - t
+                    r["bitexact"] = bool((Z.cpu().numpy().view("u4") == Zr.view("u4")).all())
+                    assert a2 == adds
+                rows.append(r)
+                log(f"table1 n={n} mu'={mu} {ydist}: {ms:.3f} ms, {adds:.3e} adds")
+    out = {"metric": "Table 1 grid (case A): strict AFMM time per product", "unit": "ms",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded generator)",
+           "paper_n2000_seconds_pentium": {str(k): v for k, v in TABLE1_PAPER_2000.items()},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -152,6 +205,8 @@ def main():
               "(the product shards by rows with no exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.table1:
+        return table1(args)
     import numpy as np
     import torch
 
