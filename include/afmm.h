@@ -133,14 +133,21 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            factor's columns; case A runs on the transposed problem),
  *            1 = base-uniform (case A only: each wave walks R rows of X with
  *            the base in a scalar register; lanes over Y's columns with a
- *            per-lane count),
+ *            per-lane count; not compiled in this build),
  *            2 = rep-uniform with base rows streamed straight into
  *            registers (no LDS panel); falls back to 0 when the base rows
- *            are not readable in 16-byte units (case B with n % 4 != 0).
+ *            are not readable in 16-byte units (case B with n % 4 != 0),
+ *            3 = rep-uniform, sparse-k: eight waves per SIMD, base panels
+ *            loaded straight into LDS, and each wave visits only the k where
+ *            one of its R rows has a non-zero count; falls back to 0 when
+ *            the base rows are not readable in 16-byte units or the base
+ *            matrix exceeds 2^31 bytes.
  *   rows_per_wave R, cols_per_lane C, waves per workgroup W, unroll U (1
  *   or 2: the repetition loop does U additions per trip; 0 means 1),
- *   k_panel (rows of the base staged per LDS panel, 8 or 16; 0 means 16):
+ *   k_panel (rows of the base staged per LDS panel, 4, 8 or 16; 0 means 16):
  *   one of the compiled combinations (afmm_config_supported tells which).
+ *   Every configuration performs the same additions in the same order, so
+ *   all give bit-identical results.
  */
 typedef struct {
     int32_t mapping;

@@ -150,6 +150,8 @@ bool config_ok(afmm_case c, const afmm_config& g) {
     const int kp = g.k_panel == 0 ? 16 : g.k_panel;
     if (g.mapping == 0)
         return rep_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
+    if (g.mapping == 3)
+        return rep_sparse_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (kp != 16) return false;
     if (u != 1) return false;
     if (g.mapping == 1)
@@ -158,14 +160,26 @@ bool config_ok(afmm_case c, const afmm_config& g) {
     return false;
 }
 
-// Built-in rule (what the autotuner picked on MI355X for both cases, used when
-// no tuning table is loaded): 16-column lanes once a tile row of 1024 columns
-// is well filled, smaller tiles below.
-afmm_config builtin_config(int64_t n) {
+// LDS-panel configurations by size: 16-column lanes once a tile row of 1024
+// columns is well filled, smaller tiles below.  Also the fallback of the
+// variants whose layout requirements a problem does not meet.
+afmm_config lds_config(int64_t n) {
     if (n > 2896) return afmm_config{0, 4, 16, 16, 1, 16};
     if (n > 1448) return afmm_config{0, 4, 4, 8, 1, 16};
     if (n > 512) return afmm_config{0, 4, 2, 4, 2, 16};
     return afmm_config{0, 2, 1, 4, 1, 16};
+}
+
+// Built-in rule, used when no tuning table is loaded: what the autotuner picked
+// on MI355X.  The sparse-k variant wins wherever the counts leave many k
+// empty for a pair of rows (case A's real factor is the sparse one here, and
+// n = 2048 needs its 16-row tiles to fill the chip); the LDS-panel variant
+// keeps n around 4096 in case B.
+afmm_config builtin_config(afmm_case c, int64_t n) {
+    if (n > 5792 || (c == AFMM_CASE_A && n > 2896)) return afmm_config{3, 2, 16, 16, 2, 8};
+    if (n > 2896) return afmm_config{0, 4, 16, 16, 1, 16};
+    if (n > 1448) return afmm_config{3, 1, 16, 16, 1, 8};
+    return lds_config(n);
 }
 
 afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
@@ -214,9 +228,14 @@ afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, flo
     }
     if (cfg.mapping == 2 && rep_direct_usable(a)) {
         AFMM_HIP(launch_rep_direct(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
-    } else if (cfg.mapping == 2 || cfg.mapping == 0) {
-        // the direct variant needs float4-readable base rows; the LDS variant takes the rest
-        const afmm_config d = cfg.mapping == 0 ? cfg : builtin_config(n);
+    } else if (cfg.mapping == 3 && rep_sparse_usable(a)) {
+        AFMM_HIP(launch_rep_sparse(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves,
+                                   cfg.unroll == 0 ? 1 : cfg.unroll,
+                                   cfg.k_panel == 0 ? 16 : cfg.k_panel, s));
+    } else if (cfg.mapping == 2 || cfg.mapping == 3 || cfg.mapping == 0) {
+        // the direct and sparse-k variants need float4-readable base rows (the
+        // sparse-k one also 31-bit offsets); the LDS-panel variant takes the rest
+        const afmm_config d = cfg.mapping == 0 ? cfg : lds_config(n);
         AFMM_HIP(launch_rep_uniform(a, d.rows_per_wave, d.cols_per_lane, d.waves,
                                     d.unroll == 0 ? 1 : d.unroll,
                                     d.k_panel == 0 ? 16 : d.k_panel, s));
@@ -341,7 +360,7 @@ afmm_config afmm_default_config(afmm_case c, int64_t n) {
         for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
             if (it->c == (int32_t)c && n >= it->lo && n <= it->hi) return it->cfg;
     }
-    return builtin_config(n);
+    return builtin_config(c, n);
 }
 
 afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void* X, const void* Y,

@@ -87,6 +87,11 @@ bool rep_uniform_supported(int R, int C, int W, int U, int KP);
 hipError_t launch_rep_direct(const StrictArgs& a, int R, int C, int W, hipStream_t s);
 bool rep_direct_supported(int R, int C, int W);
 bool rep_direct_usable(const StrictArgs& a);  // Q readable in float4 units
+// strict_sparse.hip
+hipError_t launch_rep_sparse(const StrictArgs& a, int R, int C, int W, int U, int KP,
+                             hipStream_t s);
+bool rep_sparse_supported(int R, int C, int W, int U, int KP);
+bool rep_sparse_usable(const StrictArgs& a);  // float4 rows, 31-bit byte offsets
 
 struct BaseUniformArgs {
     int n;

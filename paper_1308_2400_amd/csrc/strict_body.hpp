@@ -120,6 +120,44 @@ __device__ __forceinline__ void panel_store(const float4* buf,
     }
 }
 
+// Store a wave's R x C accumulators: column of acc[r][g*V + v] is
+// c0 + g*64*V + lane*V + v, row rw0 + r; out-of-range rows and columns are
+// not written.
+template <int R, int C, bool TRANS_OUT>
+__device__ __forceinline__ void rep_store(const float (&acc)[R][C], int n_r, int n_c,
+                                          float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
+                                          int rw0, int c0, int lane) {
+    constexpr int V = C >= 4 ? 4 : C, G = C / V;
+    if (TRANS_OUT) {
+        // the R rows of one column are consecutive in Z (z_sr == 1)
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int col = c0 + g * kWave * V + lane * V + v;
+                if (col < n_c) {
+                    float* zp = Z + (int64_t)col * z_sc + rw0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (rw0 + r < n_r) zp[r] = acc[r][g * V + v];
+                }
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = rw0 + r;
+            if (row >= n_r) break;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int col = c0 + g * kWave * V + lane * V + v;
+                    if (col < n_c) Z[(int64_t)row * z_sr + col] = acc[r][g * V + v];
+                }
+        }
+    }
+}
+
 // One tile: rows [r0, r0 + TM) x columns [c0, c0 + TN).  `lds` holds
 // LDS_FLOATS floats.  All threads of the block must call it (barriers).
 // ESC: some count byte may be 255, meaning "re-read the full int32 count";
@@ -207,9 +245,12 @@ __device__ __forceinline__ void rep_uniform_tile(
                 if (field != 0) {  // a zero Rep-factor adds nothing
                     uint32_t rep = field >> (8 * (kk & 3));
                     if (ESC && rep == 0xFFu) {
-                        const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr +
-                                                 (int64_t)(k0 + kk) * p32_sk];
-                        rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
+                        const int32_t full = __builtin_amdgcn_readfirstlane(
+                            P32[(int64_t)(rw0 + r) * p32_sr + (int64_t)(k0 + kk) * p32_sk]);
+                        // >= 255 by construction of the packed bytes; a value changed
+                        // under a running call must still end the repetition loop
+                        if (full <= 0) continue;
+                        rep = (uint32_t)full;
                     }
                     if (UNR == 2) {
                         // the same base added rep times: an odd one first, then pairs
@@ -243,35 +284,7 @@ __device__ __forceinline__ void rep_uniform_tile(
         __syncthreads();
     }
 
-    // Store: column of acc[r][g*V + v] is c0 + g*64*V + lane*V + v.
-    if (TRANS_OUT) {
-        // the R rows of one column are consecutive in Z (z_sr == 1)
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int col = c0 + g * kWave * V + lane * V + v;
-                if (col < n_c) {
-                    float* zp = Z + (int64_t)col * z_sc + rw0;
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (rw0 + r < n_r) zp[r] = acc[r][g * V + v];
-                }
-            }
-    } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int row = rw0 + r;
-            if (row >= n_r) break;
-#pragma unroll
-            for (int g = 0; g < G; ++g)
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const int col = c0 + g * kWave * V + lane * V + v;
-                    if (col < n_c) Z[(int64_t)row * z_sr + col] = acc[r][g * V + v];
-                }
-        }
-    }
+    rep_store<R, C, TRANS_OUT>(acc, n_r, n_c, Z, z_sr, z_sc, rw0, c0, lane);
 }
 
 }  // namespace afmm
@@ -332,8 +345,10 @@ __device__ __forceinline__ void direct_group(float (&acc)[R][C], const DirectBuf
             uint32_t rep = (cw[r] >> (8 * kk)) & 0xFFu;
             if (rep != 0) {
                 if (ESC && rep == 0xFFu) {
-                    const int32_t full = P32[(int64_t)(rw0 + r) * p32_sr + (int64_t)(k0 + kk) * p32_sk];
-                    rep = (uint32_t)__builtin_amdgcn_readfirstlane(full);
+                    const int32_t full = __builtin_amdgcn_readfirstlane(
+                        P32[(int64_t)(rw0 + r) * p32_sr + (int64_t)(k0 + kk) * p32_sk]);
+                    if (full <= 0) continue;  // >= 255 unless changed under the call
+                    rep = (uint32_t)full;
                 }
                 do {
 #pragma unroll

@@ -19,8 +19,8 @@ import time
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 
-CANDIDATES = [(m, r, c, w, u, kp) for m in (0, 2) for r in (2, 4, 6, 8, 16) for c in (1, 2, 4, 8, 16)
-              for w in (4, 8, 16) for u in (1, 2) for kp in (8, 16)]
+CANDIDATES = [(m, r, c, w, u, kp) for m in (0, 2, 3) for r in (1, 2, 4, 6, 8, 16)
+              for c in (1, 2, 4, 8, 16) for w in (4, 8, 16) for u in (1, 2) for kp in (4, 8, 16)]
 
 
 def _inputs(case, n, seed):

@@ -82,7 +82,10 @@ def test_config_table(afmm):
     for n in (1, 100, 256, 2048, 4096, 16384):
         assert afmm.config_supported("B", afmm.default_config("B", n))
     assert afmm.config_supported("B", (0, 8, 8, 8, 2))
-    assert not afmm.config_supported("B", (2, 8, 8, 4, 2))  # unroll 2 only in the LDS kernel
+    assert not afmm.config_supported("B", (2, 8, 8, 4, 2))  # unroll 2 only in the LDS kernels
+    assert afmm.config_supported("A", (3, 2, 16, 16, 1, 8))  # sparse-k variant
+    assert afmm.config_supported("B", (3, 4, 8, 16, 2, 16))
+    assert not afmm.config_supported("B", (3, 2, 16, 16, 1, 16))  # 128 KB of LDS: not built
     afmm.set_tuning([])
     builtin = afmm.default_config("B", 4096)
     afmm.set_tuning([("B", 1000, 5000, (0, 4, 4, 4))])

@@ -76,7 +76,10 @@ CONFIGS = [(0, 8, 8, 8), (0, 8, 8, 8, 2), (0, 4, 8, 8), (0, 8, 4, 8), (0, 8, 4, 
            (0, 8, 8, 4), (0, 8, 4, 4), (0, 8, 4, 4, 2), (0, 4, 2, 4, 2),
            (0, 4, 4, 4), (0, 4, 2, 4), (0, 2, 1, 4), (0, 4, 16, 8, 1, 8), (0, 4, 16, 8, 2, 8),
            (0, 6, 16, 4, 1, 8), (0, 8, 8, 8, 2, 8), (0, 4, 16, 16, 1, 16),
-           (2, 8, 8, 4), (2, 4, 8, 8), (2, 16, 4, 4)]
+           (2, 8, 8, 4), (2, 4, 8, 8), (2, 16, 4, 4),
+           (3, 2, 16, 16, 1, 8), (3, 2, 16, 16, 2, 8), (3, 4, 8, 16, 1, 16), (3, 4, 8, 16, 2, 16),
+           (3, 2, 8, 16, 2, 16), (3, 2, 16, 8, 1, 4), (3, 2, 16, 8, 2, 4), (3, 1, 16, 16, 1, 8)]
+SPARSE = [c for c in CONFIGS if c[0] == 3]
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
@@ -104,7 +107,34 @@ def test_direct_variant_sizes(dev, case, n):
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
-@pytest.mark.parametrize("cfg", [(0, 8, 8, 8), (2, 8, 8, 4)], ids=str)
+@pytest.mark.parametrize("n", [1, 7, 130, 515, 1000, 1100])
+def test_sparse_variant_sizes(dev, case, n):
+    """The sparse-k variant (k with all-zero counts skipped per wave) over ragged sizes,
+    dense and very sparse counts; case B with n % 4 != 0 falls back to the LDS variant."""
+    for d_int in (0.9, 0.05):
+        X, Y = _rand_case(case, n, 500 + n, int_hi=6, d_int=d_int)
+        for cfg in SPARSE:
+            _check_strict(dev, case, X, Y, config=cfg)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_counts_with_top_bit_set(dev, case):
+    """Count bytes 128..254 (no escape) in every k position: the packed count words
+    then have their top bit set, which must not leak into neighbouring counts when
+    the words are widened on the device (regression: sign extension)."""
+    n = 72
+    r = np.random.default_rng(11)
+    X, Y = _rand_case(case, n, 12, int_hi=2)
+    ints = X if case == "B" else Y
+    ints[:] = r.integers(128, 255, ints.shape)
+    ints[r.random(ints.shape) < 0.5] = 0
+    for cfg in [(0, 4, 16, 16, 1, 16), (2, 8, 8, 4)] + SPARSE:
+        _check_strict(dev, case, X, Y, config=cfg)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("cfg", [(0, 8, 8, 8), (2, 8, 8, 4), (3, 2, 16, 16, 1, 8),
+                                 (3, 4, 8, 16, 2, 16)], ids=str)
 def test_strict_large_counts_escape(dev, case, cfg):
     """Counts at and above 255 take the escape path (full int32 re-read)."""
     n = 150
@@ -175,6 +205,13 @@ def test_caseB_n4096_sampled(dev):
     _check_strict(dev, "B", X, Y, rows=_sample_rows(4096, 16))
 
 
+@pytest.mark.parametrize("cfg", SPARSE, ids=str)
+def test_caseB_n4096_sampled_sparse(dev, cfg):
+    w = gen.caseB_n4096()
+    X, Y = w.X(), w.Y()
+    _check_strict(dev, "B", X, Y, config=cfg, rows=_sample_rows(4096, 8, seed=cfg[1] + cfg[4]))
+
+
 @pytest.mark.parametrize("case", ["A", "B"])
 @pytest.mark.parametrize("d1", gen.SWEEP_D)
 @pytest.mark.parametrize("d2", gen.SWEEP_D)
@@ -194,6 +231,7 @@ def test_caseA_n16384_sampled(dev):
     X, Y = w.X(), w.Y()
     rows = [17 + 256 * t for t in range(0, 64, 8)] + [0, 16383]
     _check_strict(dev, "A", X, Y, rows=rows)
+    _check_strict(dev, "A", X, Y, config=(3, 2, 16, 16, 1, 8), rows=rows[:4])
 
 
 # --------------------------------------------------------------------------
