@@ -18,8 +18,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_ADD_TFLOPS = 78.6     # binary32 add peak: 157.3 TFLOP/s counts a (packed) FMA as 2
-PEAK_ADD_UNPACKED = 39.3   # one v_add_f32 per lane per cycle: 256 CU * 4 SIMD * 16 * 2.4 GHz
+# binary32 add peak: the published 157.3 TFLOP/s fp32 vector peak counts an FMA as
+# 2 flops, i.e. 128 lanes/clk/CU.  gfx950 reaches that rate with plain v_add_f32
+# on VGPR operands in long straight-line runs (a probe measured 90 %).
+PEAK_ADD_TFLOPS = 78.6
+# one wave64 v_add_f32 per 4 cycles per SIMD (256 CU * 4 SIMD * 16 lanes * 2.4 GHz):
+# the rate loops with short add runs, scalar branches and LDS traffic settle at
+SINGLE_ISSUE_TADDS = 39.3
 PEAK_BF16_TFLOPS = 2500.0  # dense bf16 MFMA
 
 
@@ -75,8 +80,11 @@ def cpu_baseline(w, X, Y, seconds):
             "sample": f"{k} of {w.n} rows of the same workload ({adds} additions, {dt:.1f} s)"}
 
 
-STRICT_SOURCES = ("paper_1308_2400_amd/csrc/strict_body.hpp", "paper_1308_2400_amd/csrc/strict.hip",
-                  "paper_1308_2400_amd/csrc/common.hpp")
+# the strict kernels' sources: a committed traffic measurement is used only while
+# none of them has changed since the counters were taken
+STRICT_SOURCES = tuple("paper_1308_2400_amd/csrc/" + f for f in (
+    "common.hpp", "strict_body.hpp", "sparse_body.hpp", "strict_kernels.hpp", "strict.hip",
+    "strict_part_a.hip", "strict_part_b.hip", "strict_part_c.hip", "strict_sparse.hip"))
 
 
 def strict_source_hash():
@@ -88,14 +96,15 @@ def strict_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per strict launch from the committed counter runs, if they match this kernel."""
+def measured_traffic(config):
+    """HBM bytes per strict launch from the committed counter runs, if they were taken
+    on this kernel configuration and these kernel sources."""
     path = os.path.join(ROOT, "profiles", "rep_uniform_caseB_n4096_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != strict_source_hash():
+    if d.get("source_hash") != strict_source_hash() or list(d.get("kernel_config", [])) != list(config):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -134,14 +143,14 @@ def bench_batched(args, stream, single_issued_frac):
         case, X, Y = host[t]
         Zr, _ = oracle.strict_f32(case, X[:1], Y, rows=[0], x_rows_only=True)
         ok &= bool(np.array_equal(probs[t][3][:1].cpu().numpy().view(np.uint32), Zr.view(np.uint32)))
-    frac = issued / (ms * 1e-3) / 1e12 / PEAK_ADD_UNPACKED
+    frac = issued / (ms * 1e-3) / 1e12 / SINGLE_ISSUE_TADDS
     plan.close()
     log(f"bench: batched {ms:.3f} ms, {adds / (ms * 1e-3):.3e} adds/s, issued frac {frac:.3f}")
     return {"workload": "512 products, n log-uniform [32,1024], d1,d2 ~ U(0.05,1), "
                         "integer U{0..R}, R in {3,15,63,255}, real U(-1,1)",
             "ms": ms, "useful_adds": adds, "useful_adds_per_s": adds / (ms * 1e-3),
             "issued_lane_adds": issued,
-            "issued_frac_of_unpacked_peak": frac,
+            "issued_frac_of_single_issue_rate": frac,
             "efficiency_vs_single_launch": frac / single_issued_frac,
             "bitexact_sampled_rows": ok,
             "timed": "whole plan launch (graph replay: prep, count, schedule, persistent kernel)"}
@@ -152,6 +161,33 @@ TABLE1_MU = (1, 3, 5, 7, 14, 21)
 # the paper's Table 1 times (seconds, Pentium 1.6 GHz, single thread) for context
 TABLE1_PAPER_2000 = {"ikj": 147.078, 1: 53.375, 3: 94.6875, 5: 120.8515, 7: 145.8985,
                      14: 119.516, 21: 122.491}
+
+
+def empirical_fit(rows):
+    """Empirical order of the measured times (Section 2.2 bounds the work statistically by
+    the expected number of additions): least-squares exponent b of time ~ n^b for each mu'
+    and reading, and time = t0 + adds / rate over all sizes above the smallest (where the
+    launch and the fixed passes dominate)."""
+    import numpy as np
+    fits = {}
+    for mu in sorted({r["mu_prime"] for r in rows}):
+        for yd in ("const", "uniform"):
+            sel = [r for r in rows if r["mu_prime"] == mu and r["y_nonzeros"] == yd]
+            if len(sel) < 3:
+                continue
+            ln_n = np.log([r["n"] for r in sel])
+            b, _ = np.polyfit(ln_n, np.log([r["gpu_ms"] for r in sel]), 1)
+            ba, _ = np.polyfit(ln_n, np.log([float(r["adds"]) for r in sel]), 1)
+            fits[f"{mu}_{yd}"] = {"time_exponent_in_n": float(b), "adds_exponent_in_n": float(ba)}
+    big = [r for r in rows if r["n"] > min(x["n"] for x in rows)]
+    A = np.array([[1.0, float(r["adds"])] for r in big])
+    t = np.array([r["gpu_ms"] for r in big])
+    (t0, slope), *_ = np.linalg.lstsq(A, t, rcond=None)
+    pred = A @ np.array([t0, slope])
+    r2 = 1.0 - float(((t - pred) ** 2).sum() / ((t - t.mean()) ** 2).sum())
+    return {"per_mu": fits,
+            "time_vs_adds": {"t0_ms": float(t0), "adds_per_s": float(1e3 / slope), "r2": r2,
+                             "rows": len(big)}}
 
 
 def table1(args):
@@ -194,7 +230,7 @@ def table1(args):
     out = {"metric": "Table 1 grid (case A): strict AFMM time per product", "unit": "ms",
            "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded generator)",
            "paper_n2000_seconds_pentium": {str(k): v for k, v in TABLE1_PAPER_2000.items()},
-           "rows": rows}
+           "empirical_fit": empirical_fit(rows), "rows": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -297,13 +333,15 @@ def main():
         "useful_adds": adds,
         "strict": {"ms": strict_ms, "useful_adds_per_s": adds / (strict_ms * 1e-3),
                    "effective_2n3_per_s": eff_2n3, "issued_lane_adds": issued,
-                   "issued_frac_of_unpacked_peak": issued / (strict_ms * 1e-3) / 1e12 / PEAK_ADD_UNPACKED,
+                   "issued_frac_of_single_issue_rate": issued / (strict_ms * 1e-3) / 1e12 / SINGLE_ISSUE_TADDS,
                    "bitexact_sampled_rows": bitexact},
         "count_ms": count_ms,
         "roofline": {"bound": "alu", "achieved": strict_tflops, "peak": PEAK_ADD_TFLOPS,
                      "unit": "TFLOP/s", "frac": strict_tflops / PEAK_ADD_TFLOPS,
-                     "traffic": measured_traffic(),
-                     "kernel": "rep_uniform_kernel (strict, one launch = one n=4096 product)"},
+                     "traffic": measured_traffic(cfg),
+                     "kernel": {0: "rep_uniform_kernel", 2: "rep_direct_kernel",
+                                3: "rep_sparse_kernel"}.get(cfg[0], "strict kernel")
+                               + " (strict, one launch = one n=4096 product)"},
     }
 
     if not args.no_split:
@@ -330,7 +368,7 @@ def main():
         log(f"bench: split {split_ms:.3f} ms err {err:.2e}")
 
     if not args.no_batched:
-        out["batched"] = bench_batched(args, stream, out["strict"]["issued_frac_of_unpacked_peak"])
+        out["batched"] = bench_batched(args, stream, out["strict"]["issued_frac_of_single_issue_rate"])
 
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")
