@@ -9,17 +9,17 @@
 //                 the sum of its counts (what the count-uniform mapping issues)
 //   4. schedule   one block sorts the problems by cost per tile, largest first,
 //                 and lays out the tile queue (longest-processing-time order)
-//   5. persistent about four blocks per compute unit pull tiles from the
-//                 queue with one atomic each and run the strict tile body (the
-//                 same code as the single-product kernel); every block leaves
-//                 when the queue is empty.
+//   5. persistent eight 4-wave blocks per compute unit pull tiles from the
+//                 queue with one atomic each and run a strict tile body (the
+//                 sparse-k or LDS-panel code of the single-product kernels);
+//                 every block leaves when the queue is empty.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
 
 #include "afmm.h"
-#include "strict_body.hpp"
+#include "sparse_body.hpp"
 
 namespace afmm {
 namespace {
@@ -37,16 +37,20 @@ struct BatchProblem {
     int64_t ldp;
     float* Q;     // base rows k: case A X^T, case B a padded copy of Y
     int64_t ldq;
-    int shape;    // 0: R4 C4, 1: R4 C2, 2: R2 C1 (with 4 waves)
+    int shape;    // 0: sparse-k R2 C8, 1: sparse-k R2 C4, 2: LDS panel R2 C1 (4 waves)
     int tiles_r, tiles_c;
     int64_t row_start;    // first global row in the counting kernels
     int64_t chunk_start;  // first 64 x 64 chunk in the prep kernel
     int64_t wk_off;       // first per-k weight
 };
 
-__host__ __device__ inline int shape_R(int s) { return s == 2 ? 2 : 4; }
-__host__ __device__ inline int shape_C(int s) { return s == 0 ? 4 : (s == 1 ? 2 : 1); }
+// Tile shapes: the sparse-k body (16-byte base reads, only the k with a
+// non-zero count visited) for the larger problems, the LDS-panel body with one
+// column per lane for the small ones (a 256-column tile would be mostly empty).
+__host__ __device__ inline int shape_R(int) { return 2; }
+__host__ __device__ inline int shape_C(int s) { return s == 0 ? 8 : (s == 1 ? 4 : 1); }
 inline int shape_for(int n) { return n >= 512 ? 0 : (n >= 128 ? 1 : 2); }
+constexpr int kKP0 = 4, kKP1 = 8;  // k-panel rows of the two sparse-k shapes
 
 // Largest t with start[t] <= v (start ascending, start[0] == 0).
 template <typename T>
@@ -304,34 +308,45 @@ __global__ __launch_bounds__(1024) void batch_schedule_kernel(const BatchProblem
     }
 }
 
-template <int R, int C, bool TRANS, bool ESC>
+// KP > 0: the sparse-k body with that k-panel; KP == 0: the LDS-panel body.
+// Case A runs as the transposed problem (counts Y[k,j] on rows j, Zᵀ written).
+template <int R, int C, int KP, bool TRANS, bool ESC>
 __device__ __forceinline__ void run_tile(const BatchProblem& b, int r0, int c0, float* lds) {
     const int n = b.n;
-    if (TRANS)
-        rep_uniform_tile<R, C, kBW, kBKP, true, true, ESC>(
-            n, n, n, b.P8, b.ldp, (const int32_t*)b.Y, 1, n, b.Q, b.ldq, b.Z, 1, n, r0, c0, lds);
+    const int32_t* P32 = (const int32_t*)(TRANS ? b.Y : b.X);
+    const int64_t p_sr = TRANS ? 1 : n, p_sk = TRANS ? n : 1;
+    const int64_t z_sr = TRANS ? 1 : n, z_sc = TRANS ? n : 1;
+    if constexpr (KP > 0)
+        rep_sparse_tile<R, C, kBW, KP, TRANS, ESC, 1>(n, n, n, b.P8, b.ldp, P32, p_sr, p_sk, b.Q,
+                                                      b.ldq, b.Z, z_sr, z_sc, r0, c0, lds);
     else
-        rep_uniform_tile<R, C, kBW, kBKP, true, false, ESC>(
-            n, n, n, b.P8, b.ldp, (const int32_t*)b.X, n, 1, b.Q, b.ldq, b.Z, n, 1, r0, c0, lds);
+        rep_uniform_tile<R, C, kBW, kBKP, true, TRANS, ESC>(n, n, n, b.P8, b.ldp, P32, p_sr, p_sk,
+                                                            b.Q, b.ldq, b.Z, z_sr, z_sc, r0, c0,
+                                                            lds);
 }
 
-template <int R, int C>
+template <int R, int C, int KP>
 __device__ __forceinline__ void run_shape(const BatchProblem& b, bool esc, int r0, int c0,
                                           float* lds) {
     if (b.case_id == 0) {
-        if (esc) run_tile<R, C, true, true>(b, r0, c0, lds);
-        else run_tile<R, C, true, false>(b, r0, c0, lds);
+        if (esc) run_tile<R, C, KP, true, true>(b, r0, c0, lds);
+        else run_tile<R, C, KP, true, false>(b, r0, c0, lds);
     } else {
-        if (esc) run_tile<R, C, false, true>(b, r0, c0, lds);
-        else run_tile<R, C, false, false>(b, r0, c0, lds);
+        if (esc) run_tile<R, C, KP, false, true>(b, r0, c0, lds);
+        else run_tile<R, C, KP, false, false>(b, r0, c0, lds);
     }
 }
 
-__global__ __launch_bounds__(kBW * 64) void batch_persistent_kernel(
-    const BatchProblem* __restrict__ P, int count, const int* __restrict__ order,
-    const int64_t* __restrict__ tile_start, uint32_t* __restrict__ head,
-    const uint32_t* __restrict__ esc) {
-    __shared__ float lds[RepTile<4, 4, kBW, kBKP>::LDS_FLOATS];
+constexpr int kBatchLds =
+    std::max(std::max(SparseTile<2, 8, kBW, kKP0>::LDS_FLOATS, SparseTile<2, 4, kBW, kKP1>::LDS_FLOATS),
+             RepTile<2, 1, kBW, kBKP>::LDS_FLOATS);
+
+// eight blocks (waves) per compute unit (SIMD): 64 VGPRs, 16 KB of LDS each
+__global__ __launch_bounds__(kBW * 64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+batch_persistent_kernel(const BatchProblem* __restrict__ P, int count, const int* __restrict__ order,
+                        const int64_t* __restrict__ tile_start, uint32_t* __restrict__ head,
+                        const uint32_t* __restrict__ esc) {
+    __shared__ __attribute__((aligned(16))) float lds[kBatchLds];
     __shared__ int64_t item_sh;
     const int64_t total = tile_start[count];
     for (;;) {
@@ -347,9 +362,9 @@ __global__ __launch_bounds__(kBW * 64) void batch_persistent_kernel(
         const int tr = (int)(local % b.tiles_r), tc = (int)(local / b.tiles_r);
         const bool e = esc[p] != 0;
         switch (b.shape) {
-        case 0: run_shape<4, 4>(b, e, tr * 4 * kBW, tc * 256, lds); break;
-        case 1: run_shape<4, 2>(b, e, tr * 4 * kBW, tc * 128, lds); break;
-        default: run_shape<2, 1>(b, e, tr * 2 * kBW, tc * 64, lds); break;
+        case 0: run_shape<2, 8, kKP0>(b, e, tr * 2 * kBW, tc * 512, lds); break;
+        case 1: run_shape<2, 4, kKP1>(b, e, tr * 2 * kBW, tc * 256, lds); break;
+        default: run_shape<2, 1, 0>(b, e, tr * 2 * kBW, tc * 64, lds); break;
         }
     }
 }
@@ -482,7 +497,7 @@ afmm_status afmm_plan_create(const afmm_problem* problems, int32_t count, afmm_m
     pl->total_chunks = chunks;
     pl->total_rows = rows;
     pl->total_tiles = tiles;
-    pl->persist_grid = (int)std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * 4);
+    pl->persist_grid = (int)std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * 8);
     hipError_t e = hipMalloc(&pl->mem, off);
     if (e != hipSuccess) {
         set_last_hip_error((int)e);
