@@ -111,8 +111,9 @@ afmm_status afmm_multiply_caseB(int64_t n, const int32_t *X, const float *Y, flo
  *   case B: sum over (i,k) and over j with Y[k,j] != 0 of max(X[i,k], 0)
  * Writes into device memory: *d_total (uint64, saturated at 2^64-1),
  * d_row_counts[i] = additions of row i of Z (nullable), *d_flags = the
- * AFMM_FLAG_* bits found (nullable).  Needs n * 8 bytes of workspace (or
- * NULL, see afmm_workspace_size).  Asynchronous.
+ * AFMM_FLAG_* bits found (nullable).  Needs 16 * n + 512 bytes of workspace
+ * rounded up (afmm_workspace_size(c, n, AFMM_MODE_STRICT) is enough), or NULL
+ * (see afmm_workspace_size).  Asynchronous.
  */
 afmm_status afmm_count_adds(afmm_case c, int64_t n, const void *X, const void *Y,
                             uint64_t *d_total, uint64_t *d_row_counts, uint32_t *d_flags,

@@ -111,7 +111,9 @@ SplitLayout split_layout(int64_t n) {
     return L;
 }
 
-size_t count_ws(int64_t n) { return (size_t)round_up(n * 8, 256) + 256 + 256; }
+// count scratch: per-k weights, per-row counts (when the caller passes none),
+// flags and total
+size_t count_ws(int64_t n) { return 2 * (size_t)round_up(n * 8, 256) + 256 + 256; }
 
 // Workspace from the caller or from the stream-ordered allocator.
 struct Scratch {
@@ -314,10 +316,11 @@ afmm_status afmm_count_adds(afmm_case c, int64_t n, const void* X, const void* Y
     if (st != AFMM_OK) return st;
     Scratch sc;
     if ((st = sc.get(workspace, workspace_bytes, count_ws(n), stream)) != AFMM_OK) return st;
+    const size_t vec_bytes = (size_t)round_up(n * 8, 256);
     uint64_t* wk = reinterpret_cast<uint64_t*>(sc.at(0));
-    uint32_t* flags = d_flags ? d_flags
-                              : reinterpret_cast<uint32_t*>(sc.at((size_t)round_up(n * 8, 256)));
-    AFMM_HIP(launch_count((int)c, (int)n, X, Y, wk, d_row_counts, d_total, flags, stream));
+    uint64_t* rows = d_row_counts ? d_row_counts : reinterpret_cast<uint64_t*>(sc.at(vec_bytes));
+    uint32_t* flags = d_flags ? d_flags : reinterpret_cast<uint32_t*>(sc.at(2 * vec_bytes));
+    AFMM_HIP(launch_count((int)c, (int)n, X, Y, wk, rows, d_total, flags, stream));
     return AFMM_OK;
 }
 

@@ -143,25 +143,55 @@ __global__ void count_zero_kernel(uint64_t* total, uint32_t* flags) {
     *flags = 0;
 }
 
+// One matrix row of n 32-bit entries, four per thread per step with the loads
+// of up to four steps issued before any is used (rows are 16-byte aligned when
+// vec is set, i.e. n % 4 == 0); the rest of the row one entry at a time.
+// f(k, bits) is called once per entry k, in no particular order.
+template <typename F>
+__device__ __forceinline__ void for_row(const uint32_t* __restrict__ row, int n, bool vec, F&& f) {
+    const int t = threadIdx.x;
+    const int nv = vec ? n / 4 : 0;
+    for (int base = 0; base < nv; base += 4 * 256) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = base + u * 256 + t;
+            v[u] = c < nv ? reinterpret_cast<const uint4*>(row)[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = base + u * 256 + t;
+            if (c < nv) {
+                f(4 * c + 0, v[u].x);
+                f(4 * c + 1, v[u].y);
+                f(4 * c + 2, v[u].z);
+                f(4 * c + 3, v[u].w);
+            }
+        }
+    }
+    for (int k = 4 * nv + t; k < n; k += 256) f(k, row[k]);
+}
+
 // wk[k] = weight of row k of the post-factor Y:
 //   case A: sum_j max(Y[k,j], 0)     (Y integer; < n * 2^31, no overflow)
 //   case B: #{j : Y[k,j] != 0}       (Y real)
-__global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, const void* __restrict__ Yv,
+__global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, bool vec,
+                                                         const void* __restrict__ Yv,
                                                          uint64_t* __restrict__ wk,
                                                          uint32_t* __restrict__ flags) {
     const int k = blockIdx.x;
+    const uint32_t* y = (const uint32_t*)Yv + (int64_t)k * n;
     uint64_t s = 0;
     uint32_t fl = 0;
     if (case_id == 0) {
-        const int32_t* y = (const int32_t*)Yv + (int64_t)k * n;
-        for (int j = threadIdx.x; j < n; j += 256) {
-            const int32_t v = y[j];
+        for_row(y, n, vec, [&](int, uint32_t bits) {
+            const int32_t v = (int32_t)bits;
             fl |= int_flags(v);
             if (v > 0) s += (uint64_t)v;
-        }
+        });
     } else {
-        const float* y = (const float*)Yv + (int64_t)k * n;
-        for (int j = threadIdx.x; j < n; j += 256) s += (y[j] != 0.0f) ? 1u : 0u;
+        // a binary32 entry is non-zero unless its bits are +0 or -0
+        for_row(y, n, vec, [&](int, uint32_t bits) { s += (bits & 0x7FFFFFFFu) != 0u ? 1u : 0u; });
     }
     s = block_sum_sat(s, fl);
     if (threadIdx.x == 0) {
@@ -173,46 +203,64 @@ __global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, co
 // Row counts of Section 2.2 summed exactly:
 //   case A: r_i = sum_k [X[i,k] != 0] * wk[k]
 //   case B: r_i = sum_k max(X[i,k], 0) * wk[k]
-__global__ __launch_bounds__(256) void count_rows_kernel(int case_id, int n, const void* __restrict__ Xv,
+// No row sum can overflow 64 bits for n <= 2^16: a case-A weight is below
+// n * 2^31 <= 2^47, a case-B term below 2^31 * n <= 2^47, and a row has at most
+// 2^16 terms.  Only the total over rows can; count_total_kernel saturates it.
+__global__ __launch_bounds__(256) void count_rows_kernel(int case_id, int n, bool vec,
+                                                        const void* __restrict__ Xv,
                                                         const uint64_t* __restrict__ wk,
                                                         uint64_t* __restrict__ rows,
-                                                        uint64_t* __restrict__ total,
                                                         uint32_t* __restrict__ flags) {
     const int i = blockIdx.x;
+    const uint32_t* x = (const uint32_t*)Xv + (int64_t)i * n;
     uint64_t s = 0;
     uint32_t fl = 0;
     if (case_id == 0) {
-        const float* x = (const float*)Xv + (int64_t)i * n;
-        for (int k = threadIdx.x; k < n; k += 256)
-            if (x[k] != 0.0f) s = sat_add(s, wk[k], fl);
+        for_row(x, n, vec, [&](int k, uint32_t bits) {
+            if ((bits & 0x7FFFFFFFu) != 0u) s += wk[k];
+        });
     } else {
-        const int32_t* x = (const int32_t*)Xv + (int64_t)i * n;
-        for (int k = threadIdx.x; k < n; k += 256) {
-            const int32_t v = x[k];
+        for_row(x, n, vec, [&](int k, uint32_t bits) {
+            const int32_t v = (int32_t)bits;
             fl |= int_flags(v);
-            if (v > 0) s = sat_add(s, sat_mul((uint64_t)v, wk[k], fl), fl);
-        }
+            // wk[k] <= n <= 2^16 here: a 32 x 32 -> 64-bit product
+            if (v > 0) s += (uint64_t)(uint32_t)v * (uint32_t)wk[k];
+        });
     }
     s = block_sum_sat(s, fl);
     if (threadIdx.x == 0) {
-        if (rows) rows[i] = s;
-        const unsigned long long old = atomicAdd((unsigned long long*)total, (unsigned long long)s);
-        if (old + s < old) fl |= kOverflow;
+        rows[i] = s;
         if (fl) atomicOr(flags, fl);
     }
 }
 
-__global__ void count_finalize_kernel(uint64_t* total, const uint32_t* flags) {
-    if (*flags & kOverflow) *total = ~0ull;
+// Total of the row counts, saturating at 2^64 - 1 (one block; the rows are
+// summed here rather than by one atomic per row, which serialises on a
+// single address).
+__global__ __launch_bounds__(256) void count_total_kernel(int n, const uint64_t* __restrict__ rows,
+                                                         uint64_t* __restrict__ total,
+                                                         uint32_t* __restrict__ flags) {
+    uint64_t s = 0;
+    uint32_t fl = 0;
+    for (int i = threadIdx.x; i < n; i += 256) s = sat_add(s, rows[i], fl);
+    s = block_sum_sat(s, fl);
+    if (threadIdx.x == 0) {
+        if (fl & kOverflow) atomicOr(flags, kOverflow);
+        *total = s;  // saturated already when the sum overflowed
+    }
 }
 
 hipError_t launch_count(int case_id, int n, const void* X, const void* Y, uint64_t* wk,
                         uint64_t* rows, uint64_t* total, uint32_t* flags, hipStream_t s) {
+    // rows: n entries (the caller's per-row output or scratch)
     hipLaunchKernelGGL(count_zero_kernel, dim3(1), dim3(1), 0, s, total, flags);
-    hipLaunchKernelGGL(count_kstat_kernel, dim3(n), dim3(256), 0, s, case_id, n, Y, wk, flags);
-    hipLaunchKernelGGL(count_rows_kernel, dim3(n), dim3(256), 0, s, case_id, n, X, wk, rows,
-                       total, flags);
-    hipLaunchKernelGGL(count_finalize_kernel, dim3(1), dim3(1), 0, s, total, flags);
+    // 16-byte row loads need every row start 16-byte aligned
+    const bool vy = n % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+    const bool vx = n % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    hipLaunchKernelGGL(count_kstat_kernel, dim3(n), dim3(256), 0, s, case_id, n, vy, Y, wk, flags);
+    hipLaunchKernelGGL(count_rows_kernel, dim3(n), dim3(256), 0, s, case_id, n, vx, X, wk, rows,
+                       flags);
+    hipLaunchKernelGGL(count_total_kernel, dim3(1), dim3(256), 0, s, n, rows, total, flags);
     return hipGetLastError();
 }
 
