@@ -36,10 +36,18 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [i64, vp, vp, vp, vp, i64, ci]
             f.restype = u64
+            f = getattr(L, name + "_ex")
+            f.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, ci]
+            f.restype = u64
         L.afmm_oracle_product_f64.argtypes = [ci, i64, vp, vp, vp, vp, i64, ci]
         L.afmm_oracle_product_f64.restype = None
+        L.afmm_oracle_product_f64_ex.argtypes = [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64,
+                                                 vp, i64, ci]
+        L.afmm_oracle_product_f64_ex.restype = None
         L.afmm_oracle_count.argtypes = [ci, i64, vp, vp, vp, vp]
         L.afmm_oracle_count.restype = ctypes.c_uint
+        L.afmm_oracle_count_ex.argtypes = [ci, i64, i64, i64, vp, i64, vp, i64, vp, vp]
+        L.afmm_oracle_count_ex.restype = ctypes.c_uint
         L.afmm_oracle_split_bf16x3.argtypes = [i64, vp, vp, vp, vp]
         L.afmm_oracle_split_bf16x3.restype = None
         _lib = L
@@ -58,24 +66,35 @@ def _rows_arg(rows):
     return r, r.ctypes.data
 
 
+def _shapes(X, Y, r, x_rows_only):
+    """(m, kd, n, output rows) of X (m x kd, or the listed rows only) times Y (kd x n)."""
+    kd, n = Y.shape
+    assert X.shape[1] == kd, (X.shape, Y.shape)
+    m = X.shape[0] if not x_rows_only else None
+    nout = (m if r is None else len(r))
+    if x_rows_only:
+        assert r is not None and X.shape[0] == len(r)
+        m = int(r.max()) + 1 if len(r) else 0
+    return m, kd, n, nout
+
+
 def _strict(name, X, Y, xdt, ydt, rows, x_rows_only):
+    """Rectangular strict loop (X m x kd, Y kd x n; the square case is m = kd = n)."""
     X = _c(X, xdt)
     Y = _c(Y, ydt)
-    n = Y.shape[0]
-    assert Y.shape == (n, n)
     r, rp = _rows_arg(rows)
-    m = n if r is None else len(r)
-    assert X.shape == ((m, n) if x_rows_only else (n, n))
-    Z = np.empty((m, n), dtype=np.float32)
-    adds = getattr(lib(), name)(n, X.ctypes.data, Y.ctypes.data, Z.ctypes.data, rp,
-                                m, 1 if x_rows_only else 0)
+    m, kd, n, nout = _shapes(X, Y, r, x_rows_only)
+    Z = np.empty((nout, n), dtype=np.float32)
+    adds = getattr(lib(), name + "_ex")(m, kd, n, X.ctypes.data, kd, Y.ctypes.data, n,
+                                        Z.ctypes.data, n, rp, nout, 1 if x_rows_only else 0)
     if adds == U64_MAX:
         raise RuntimeError("CPU flushes denormals (FTZ/DAZ set); oracle results void")
     return Z, int(adds)
 
 
 def caseA_f32(X, Y, rows=None, x_rows_only=False):
-    """Strict FP32 case A in the paper's (i,k,j,p) order -> (Z rows, additions)."""
+    """Strict FP32 case A in the paper's (i,k,j,p) order -> (Z rows, additions).
+    X is m x kd (or only the listed rows with x_rows_only), Y is kd x n."""
     return _strict("afmm_oracle_caseA_f32", X, Y, np.float32, np.int32, rows, x_rows_only)
 
 
@@ -93,12 +112,12 @@ def product_f64(case, X, Y, rows=None, x_rows_only=False):
     xdt, ydt = (np.float32, np.int32) if case == "A" else (np.int32, np.float32)
     X = _c(X, xdt)
     Y = _c(Y, ydt)
-    n = Y.shape[0]
     r, rp = _rows_arg(rows)
-    m = n if r is None else len(r)
-    Z = np.empty((m, n), dtype=np.float64)
-    lib().afmm_oracle_product_f64(0 if case == "A" else 1, n, X.ctypes.data, Y.ctypes.data,
-                                  Z.ctypes.data, rp, m, 1 if x_rows_only else 0)
+    m, kd, n, nout = _shapes(X, Y, r, x_rows_only)
+    Z = np.empty((nout, n), dtype=np.float64)
+    lib().afmm_oracle_product_f64_ex(0 if case == "A" else 1, m, kd, n, X.ctypes.data, kd,
+                                     Y.ctypes.data, n, Z.ctypes.data, n, rp, nout,
+                                     1 if x_rows_only else 0)
     return Z
 
 
@@ -112,11 +131,11 @@ def count(case, X, Y):
     xdt, ydt = (np.float32, np.int32) if case == "A" else (np.int32, np.float32)
     X = _c(X, xdt)
     Y = _c(Y, ydt)
-    n = Y.shape[0]
+    m, kd, n, _ = _shapes(X, Y, None, False)
     tot = np.zeros(1, dtype=np.uint64)
-    rows = np.zeros(n, dtype=np.uint64)
-    flags = lib().afmm_oracle_count(0 if case == "A" else 1, n, X.ctypes.data, Y.ctypes.data,
-                                    tot.ctypes.data, rows.ctypes.data)
+    rows = np.zeros(m, dtype=np.uint64)
+    flags = lib().afmm_oracle_count_ex(0 if case == "A" else 1, m, kd, n, X.ctypes.data, kd,
+                                       Y.ctypes.data, n, tot.ctypes.data, rows.ctypes.data)
     return int(tot[0]), rows, int(flags)
 
 

@@ -25,24 +25,25 @@ static inline int64_t row_of(const int64_t *rows, int64_t t)
 /*
  * Section 2, Case-A loop: for each row I, for each K, Base = X[I,K]; a zero
  * Base moves on to the next K; otherwise for each J, Rep-factor = Y[K,J] and
- * Z[I,J] receives Base that many times (readings R1, R3-R7).
+ * Z[I,J] receives Base that many times (readings R1, R3-R7; the I, K and J
+ * bounds m, kd, n taken separately, reading R9).
  */
-uint64_t afmm_oracle_caseA_f32(int64_t n, const float *X, const int32_t *Y,
-                               float *Z, const int64_t *rows, int64_t nrows,
-                               int x_rows_only)
+uint64_t afmm_oracle_caseA_f32_ex(int64_t m, int64_t kd, int64_t n, const float *X, int64_t ldx,
+                                  const int32_t *Y, int64_t ldy, float *Z, int64_t ldz,
+                                  const int64_t *rows, int64_t nrows, int x_rows_only)
 {
     if (!fpenv_ok()) return UINT64_MAX;
-    if (!rows) nrows = n;
+    if (!rows) nrows = m;
     uint64_t adds = 0;
     for (int64_t t = 0; t < nrows; ++t) {
         const int64_t i = row_of(rows, t);
-        const float *xrow = X + (x_rows_only ? t : i) * n;
-        float *zrow = Z + t * n;
+        const float *xrow = X + (x_rows_only ? t : i) * ldx;
+        float *zrow = Z + t * ldz;
         for (int64_t j = 0; j < n; ++j) zrow[j] = 0.0f;          /* Z starts at zero */
-        for (int64_t k = 0; k < n; ++k) {
+        for (int64_t k = 0; k < kd; ++k) {
             const float base = xrow[k];
             if (base == 0.0f) continue;                            /* zero Base: next K */
-            const int32_t *yrow = Y + k * n;
+            const int32_t *yrow = Y + k * ldy;
             for (int64_t j = 0; j < n; ++j) {
                 const int32_t rep = yrow[j];                       /* Rep-factor */
                 for (int32_t p = 0; p < rep; ++p) {
@@ -55,28 +56,35 @@ uint64_t afmm_oracle_caseA_f32(int64_t n, const float *X, const int32_t *Y,
     return adds;
 }
 
+uint64_t afmm_oracle_caseA_f32(int64_t n, const float *X, const int32_t *Y,
+                               float *Z, const int64_t *rows, int64_t nrows,
+                               int x_rows_only)
+{
+    return afmm_oracle_caseA_f32_ex(n, n, n, X, n, Y, n, Z, n, rows, nrows, x_rows_only);
+}
+
 /*
  * Section 2, Case-B loop: Rep-factor = X[I,K]; for each J, Base = Y[K,J]; a
  * zero Base is skipped for that J only (reading R2); otherwise Z[I,J]
  * receives Base Rep-factor times.  A Rep-factor <= 0 adds nothing for any J
  * (reading R5), so testing it once per K changes no result and no count.
  */
-uint64_t afmm_oracle_caseB_f32(int64_t n, const int32_t *X, const float *Y,
-                               float *Z, const int64_t *rows, int64_t nrows,
-                               int x_rows_only)
+uint64_t afmm_oracle_caseB_f32_ex(int64_t m, int64_t kd, int64_t n, const int32_t *X, int64_t ldx,
+                                  const float *Y, int64_t ldy, float *Z, int64_t ldz,
+                                  const int64_t *rows, int64_t nrows, int x_rows_only)
 {
     if (!fpenv_ok()) return UINT64_MAX;
-    if (!rows) nrows = n;
+    if (!rows) nrows = m;
     uint64_t adds = 0;
     for (int64_t t = 0; t < nrows; ++t) {
         const int64_t i = row_of(rows, t);
-        const int32_t *xrow = X + (x_rows_only ? t : i) * n;
-        float *zrow = Z + t * n;
+        const int32_t *xrow = X + (x_rows_only ? t : i) * ldx;
+        float *zrow = Z + t * ldz;
         for (int64_t j = 0; j < n; ++j) zrow[j] = 0.0f;
-        for (int64_t k = 0; k < n; ++k) {
+        for (int64_t k = 0; k < kd; ++k) {
             const int32_t rep = xrow[k];                           /* Rep-factor */
             if (rep <= 0) continue;
-            const float *yrow = Y + k * n;
+            const float *yrow = Y + k * ldy;
             for (int64_t j = 0; j < n; ++j) {
                 const float base = yrow[j];                        /* Base */
                 if (base == 0.0f) continue;                        /* skip this J only */
@@ -90,35 +98,49 @@ uint64_t afmm_oracle_caseB_f32(int64_t n, const int32_t *X, const float *Y,
     return adds;
 }
 
+uint64_t afmm_oracle_caseB_f32(int64_t n, const int32_t *X, const float *Y,
+                               float *Z, const int64_t *rows, int64_t nrows,
+                               int x_rows_only)
+{
+    return afmm_oracle_caseB_f32_ex(n, n, n, X, n, Y, n, Z, n, rows, nrows, x_rows_only);
+}
+
 /*
  * The product the method computes (abstract; Section 2.1, point 1):
  * Z[i,j] = sum_k X[i,k] * Y[k,j], here in binary64 with k ascending.  Every
  * term is exact in binary64 (a binary32 times an integer below 2^29).
  */
-void afmm_oracle_product_f64(int case_id, int64_t n, const void *X, const void *Y,
-                             double *Z, const int64_t *rows, int64_t nrows,
-                             int x_rows_only)
+void afmm_oracle_product_f64_ex(int case_id, int64_t m, int64_t kd, int64_t n, const void *X,
+                                int64_t ldx, const void *Y, int64_t ldy, double *Z, int64_t ldz,
+                                const int64_t *rows, int64_t nrows, int x_rows_only)
 {
-    if (!rows) nrows = n;
+    if (!rows) nrows = m;
     for (int64_t t = 0; t < nrows; ++t) {
         const int64_t i = row_of(rows, t);
-        const int64_t xr = (x_rows_only ? t : i) * n;
-        double *zrow = Z + t * n;
+        const int64_t xr = (x_rows_only ? t : i) * ldx;
+        double *zrow = Z + t * ldz;
         for (int64_t j = 0; j < n; ++j) zrow[j] = 0.0;
-        for (int64_t k = 0; k < n; ++k) {
+        for (int64_t k = 0; k < kd; ++k) {
             double x;
             if (case_id == 0) x = (double)((const float *)X)[xr + k];
             else x = (double)((const int32_t *)X)[xr + k];
             if (x == 0.0) continue;
             if (case_id == 0) {
-                const int32_t *yrow = (const int32_t *)Y + k * n;
+                const int32_t *yrow = (const int32_t *)Y + k * ldy;
                 for (int64_t j = 0; j < n; ++j) zrow[j] += x * (double)yrow[j];
             } else {
-                const float *yrow = (const float *)Y + k * n;
+                const float *yrow = (const float *)Y + k * ldy;
                 for (int64_t j = 0; j < n; ++j) zrow[j] += x * (double)yrow[j];
             }
         }
     }
+}
+
+void afmm_oracle_product_f64(int case_id, int64_t n, const void *X, const void *Y,
+                             double *Z, const int64_t *rows, int64_t nrows,
+                             int x_rows_only)
+{
+    afmm_oracle_product_f64_ex(case_id, n, n, n, X, n, Y, n, Z, n, rows, nrows, x_rows_only);
 }
 
 typedef unsigned __int128 u128;
@@ -145,39 +167,40 @@ static void int_flags(int32_t v, unsigned *flags)
  * repeated by; summing that count exactly over the matrix gives, per row i,
  *   case A: r_i = sum_k [X[i,k] != 0] * sum_j max(Y[k,j], 0)
  *   case B: r_i = sum_k max(X[i,k], 0) * #{j : Y[k,j] != 0}
- * and the total is sum_i r_i.
+ * and the total is sum_i r_i (i < m, k < kd, j < n).
  */
-unsigned afmm_oracle_count(int case_id, int64_t n, const void *X, const void *Y,
-                           uint64_t *total, uint64_t *row_counts)
+unsigned afmm_oracle_count_ex(int case_id, int64_t m, int64_t kd, int64_t n, const void *X,
+                              int64_t ldx, const void *Y, int64_t ldy, uint64_t *total,
+                              uint64_t *row_counts)
 {
     unsigned flags = 0;
     /* wk[k]: weight of the post-factor's row k (its positive sum in case A,
      * its number of non-zeros in case B); at most n * 2^31 < 2^64. */
-    uint64_t *wk = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
+    uint64_t *wk = (uint64_t *)malloc((size_t)(kd > 0 ? kd : 1) * sizeof(uint64_t));
     if (!wk) return AFMM_ORACLE_OVERFLOW;
-    for (int64_t k = 0; k < n; ++k) {
+    for (int64_t k = 0; k < kd; ++k) {
         u128 s = 0;
         for (int64_t j = 0; j < n; ++j) {
             if (case_id == 0) {
-                const int32_t v = ((const int32_t *)Y)[k * n + j];
+                const int32_t v = ((const int32_t *)Y)[k * ldy + j];
                 int_flags(v, &flags);
                 if (v > 0) s += (u128)v;
             } else {
-                const float v = ((const float *)Y)[k * n + j];
+                const float v = ((const float *)Y)[k * ldy + j];
                 if (v != 0.0f) s += 1;
             }
         }
         wk[k] = (uint64_t)s;
     }
     u128 tot = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < m; ++i) {
         u128 r = 0;
-        for (int64_t k = 0; k < n; ++k) {
+        for (int64_t k = 0; k < kd; ++k) {
             if (case_id == 0) {
-                const float x = ((const float *)X)[i * n + k];
+                const float x = ((const float *)X)[i * ldx + k];
                 if (x != 0.0f) r += (u128)wk[k];
             } else {
-                const int32_t x = ((const int32_t *)X)[i * n + k];
+                const int32_t x = ((const int32_t *)X)[i * ldx + k];
                 int_flags(x, &flags);
                 if (x > 0) r += (u128)(uint64_t)x * (u128)wk[k];
             }
@@ -189,6 +212,12 @@ unsigned afmm_oracle_count(int case_id, int64_t n, const void *X, const void *Y,
     free(wk);
     if (!fpenv_ok()) flags |= AFMM_ORACLE_FPENV;
     return flags;
+}
+
+unsigned afmm_oracle_count(int case_id, int64_t n, const void *X, const void *Y,
+                           uint64_t *total, uint64_t *row_counts)
+{
+    return afmm_oracle_count_ex(case_id, n, n, n, X, n, Y, n, total, row_counts);
 }
 
 /* Round-to-nearest-even of a binary32 to its upper 16 bits (bfloat16). */

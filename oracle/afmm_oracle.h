@@ -7,8 +7,12 @@
  * the smoke check and the benchmark's CPU-baseline leg may load it; the
  * product library never does, and the two share no code.
  *
- * Matrices are dense n x n, row-major, 0-based (Section 2 recommends the
- * plain two-dimensional array).  X is the pre-factor, Y the post-factor.
+ * Matrices are dense, row-major, 0-based (Section 2 recommends the plain
+ * two-dimensional array).  X is the pre-factor, Y the post-factor.  The
+ * paper's matrices are n x n; the _ex forms take X as m x kd with leading
+ * dimension ldx, Y as kd x n with ldy and Z as m x n with ldz (element (r, c)
+ * of X at X[r * ldx + c]), and the square forms are m = kd = n with every
+ * leading dimension n.
  *   Case A: X real (float), Y integer (int32)   -- Section 2, Case-A loop.
  *   Case B: X integer (int32), Y real (float)   -- Section 2, Case-B loop.
  *
@@ -30,6 +34,9 @@
  *      comparisons and index arithmetic are not counted.
  *  R8  Floating point is IEEE binary32 (binary64 for the true product),
  *      round to nearest even, denormals kept, no contraction.
+ *  R9  Rectangular shapes run the same loops with the I, K and J bounds
+ *      taken separately (m, kd, n): the product of an m x kd and a kd x n
+ *      matrix, which is what the loops compute once their bounds differ.
  */
 #ifndef AFMM_ORACLE_H
 #define AFMM_ORACLE_H
@@ -65,6 +72,18 @@ uint64_t afmm_oracle_caseB_f32(int64_t n, const int32_t *X, const float *Y,
                                int x_rows_only);
 
 /*
+ * Rectangular forms of the two strict loops (reading R9): rows == NULL means
+ * all m rows; the t-th listed row goes to Z[t * ldz + j]; with x_rows_only
+ * the t-th listed row of X is read from X[t * ldx + k].
+ */
+uint64_t afmm_oracle_caseA_f32_ex(int64_t m, int64_t kd, int64_t n, const float *X, int64_t ldx,
+                                  const int32_t *Y, int64_t ldy, float *Z, int64_t ldz,
+                                  const int64_t *rows, int64_t nrows, int x_rows_only);
+uint64_t afmm_oracle_caseB_f32_ex(int64_t m, int64_t kd, int64_t n, const int32_t *X, int64_t ldx,
+                                  const float *Y, int64_t ldy, float *Z, int64_t ldz,
+                                  const int64_t *rows, int64_t nrows, int x_rows_only);
+
+/*
  * True product Z = X . Y in binary64, k ascending, for the listed rows
  * (rows == NULL: all), case_id 0 = A (X float, Y int32), 1 = B (X int32,
  * Y float).  With x_rows_only the t-th listed row of X is X[t * n + k].
@@ -72,6 +91,9 @@ uint64_t afmm_oracle_caseB_f32(int64_t n, const int32_t *X, const float *Y,
 void afmm_oracle_product_f64(int case_id, int64_t n, const void *X, const void *Y,
                              double *Z, const int64_t *rows, int64_t nrows,
                              int x_rows_only);
+void afmm_oracle_product_f64_ex(int case_id, int64_t m, int64_t kd, int64_t n, const void *X,
+                                int64_t ldx, const void *Y, int64_t ldy, double *Z, int64_t ldz,
+                                const int64_t *rows, int64_t nrows, int x_rows_only);
 
 /*
  * Number of additions the algorithm performs, from its definition summed in
@@ -85,6 +107,10 @@ void afmm_oracle_product_f64(int case_id, int64_t n, const void *X, const void *
  */
 unsigned afmm_oracle_count(int case_id, int64_t n, const void *X, const void *Y,
                            uint64_t *total, uint64_t *row_counts);
+/* Rectangular form (reading R9): m rows of Z, kd, n; row_counts has m entries. */
+unsigned afmm_oracle_count_ex(int case_id, int64_t m, int64_t kd, int64_t n, const void *X,
+                              int64_t ldx, const void *Y, int64_t ldy, uint64_t *total,
+                              uint64_t *row_counts);
 
 /*
  * Split of binary32 values into three bfloat16 terms, each the round-to-

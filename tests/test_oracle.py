@@ -374,3 +374,104 @@ def test_strict_error_vs_true_product_is_bounded():
     bound = (m * U / (1 - m * U)) * (np.abs(X).astype(np.float64) @ np.abs(Y).astype(np.float64))
     assert np.all(np.abs(Z32 - Z64) <= bound)
     assert 1e-8 < oracle.rel_frobenius(Z32, Z64) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# Rectangular shapes (the same loops with separate i, k, j bounds)
+
+def _rng_rect(case, m, kd, n, seed, int_hi=5, dens=0.6):
+    r = np.random.default_rng(seed)
+    xs, ys = (m, kd), (kd, n)
+    if case == "A":
+        X = r.standard_normal(xs).astype(np.float32)
+        X[r.random(xs) > dens] = 0
+        Y = r.integers(0, int_hi + 1, ys).astype(np.int32)
+        Y[r.random(ys) > dens] = 0
+    else:
+        X = r.integers(0, int_hi + 1, xs).astype(np.int32)
+        X[r.random(xs) > dens] = 0
+        Y = r.standard_normal(ys).astype(np.float32)
+        Y[r.random(ys) > dens] = 0
+    return X, Y
+
+
+RECT = [(1, 5, 3), (4, 1, 6), (3, 7, 2), (6, 3, 1), (2, 8, 5)]
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("m,kd,n", RECT)
+def test_rect_bruteforce_exact_rational(case, m, kd, n):
+    """m x kd times kd x n: both oracles within their rounding bounds of the exact
+    rational product, and the count equal to brute force."""
+    X, Y = _rng_rect(case, m, kd, n, 100 * m + 10 * kd + n)
+    Z64 = oracle.product_f64(case, X, Y)
+    Z32, adds = oracle.strict_f32(case, X, Y)
+    assert Z32.shape == Z64.shape == (m, n)
+    ints = Y if case == "A" else X
+    brute = 0
+    for i in range(m):
+        for j in range(n):
+            terms = [Fraction(float(X[i, k])) * Fraction(float(Y[k, j])) for k in range(kd)]
+            exact = sum(terms, Fraction(0))
+            s_abs = sum(abs(t) for t in terms)
+            g64 = (kd * 2.0 ** -53) / (1 - kd * 2.0 ** -53)
+            assert abs(Fraction(float(Z64[i, j])) - exact) <= Fraction(g64) * s_abs
+            reps = sum(int(ints[k, j] if case == "A" else ints[i, k]) for k in range(kd)
+                       if X[i, k] != 0 and Y[k, j] != 0)
+            brute += reps
+            g32 = (max(reps - 1, 0) * U) / (1 - max(reps - 1, 0) * U)
+            assert abs(Fraction(float(Z32[i, j])) - exact) <= Fraction(g32) * s_abs
+    total, rows, flags = oracle.count(case, X, Y)
+    assert adds == brute == total == int(rows.sum()) and rows.shape == (m,) and flags == 0
+
+
+def test_rect_transpose_duality():
+    """Case A on an m x kd and a kd x n factor adds, per element, what case B adds on
+    the transposed factors (n x kd times kd x m)."""
+    X, Y = _rng_rect("A", 13, 29, 7, 5)
+    ZA, aA = oracle.caseA_f32(X, Y)
+    ZB, aB = oracle.caseB_f32(np.ascontiguousarray(Y.T), np.ascontiguousarray(X.T))
+    assert aA == aB and ZA.shape == (13, 7) and ZB.shape == (7, 13)
+    assert np.array_equal(ZA.view(np.uint32), np.ascontiguousarray(ZB.T).view(np.uint32))
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_rect_blocks_of_square_product(case):
+    """Rows of Z depend only on their row of X, columns only on their column of Y
+    (Section 2.1): a rectangular product of row and column blocks equals the same block
+    of the square product, bit for bit, and so do the counts of its rows."""
+    X, Y = _rng_case(case, 40, 31, int_hi=6, dyadic=False)
+    Z, _ = oracle.strict_f32(case, X, Y)
+    Zb, _ = oracle.strict_f32(case, X[5:17], Y[:, 9:30])
+    assert np.array_equal(Zb.view(np.uint32), Z[5:17, 9:30].view(np.uint32))
+    Zr, _ = oracle.strict_f32(case, X[:, :40], Y[:40, :])
+    assert np.array_equal(Zr.view(np.uint32), Z.view(np.uint32))
+    # columns beyond a kd-slice change: a shorter reduction is a different product
+    Zk, _ = oracle.strict_f32(case, X[:, :20], Y[:20, :])
+    Zk2, _ = oracle.strict_f32(case, np.hstack([X[:, :20], 0 * X[:, 20:]]), Y)
+    assert np.array_equal(Zk.view(np.uint32), Zk2.view(np.uint32))
+
+
+def test_rect_leading_dimensions_in_c():
+    """The C oracle's leading-dimension arguments: a product read out of padded buffers
+    equals the compact one, and nothing outside the m x n block of Z is written."""
+    import ctypes
+    X, Y = _rng_rect("B", 9, 14, 6, 77)
+    Zc, ac = oracle.caseB_f32(X, Y)
+    ldx, ldy, ldz = 17, 11, 10
+    Xp = np.full((9, ldx), 123456, np.int32)
+    Xp[:, :14] = X
+    Yp = np.full((14, ldy), np.nan, np.float32)
+    Yp[:, :6] = Y
+    Zp = np.full((9, ldz), -7.0, np.float32)
+    a = oracle.lib().afmm_oracle_caseB_f32_ex(9, 14, 6, Xp.ctypes.data, ldx, Yp.ctypes.data, ldy,
+                                              Zp.ctypes.data, ldz, None, 9, 0)
+    assert a == ac
+    assert np.array_equal(Zp[:, :6].view(np.uint32), Zc.view(np.uint32))
+    assert (Zp[:, 6:] == -7.0).all()
+    tot = np.zeros(1, np.uint64)
+    rows = np.zeros(9, np.uint64)
+    fl = oracle.lib().afmm_oracle_count_ex(1, 9, 14, 6, Xp.ctypes.data, ldx, Yp.ctypes.data, ldy,
+                                           tot.ctypes.data, rows.ctypes.data)
+    assert fl == 0 and int(tot[0]) == ac
+    del ctypes
