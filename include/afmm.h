@@ -119,6 +119,37 @@ afmm_status afmm_count_adds(afmm_case c, int64_t n, const void *X, const void *Y
                             uint64_t *d_total, uint64_t *d_row_counts, uint32_t *d_flags,
                             void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Rectangular and strided forms.  The paper's matrices are n x n (Section 2);
+ * its loops run unchanged with separate bounds for i, k and j, which is the
+ * product of an m x k pre-factor and a k x n post-factor.  Matrices are
+ * row-major with leading dimensions (element (r, c) of X at X[r * ldx + c]):
+ * X is m x k (ldx >= k), Y is k x n (ldy >= n), Z is m x n (ldz >= n); 1 <=
+ * m, k, n <= AFMM_MAX_N and every leading dimension <= 2^28.  Only the m x n
+ * block of Z is written (its padding keeps its contents); padding in X and Y
+ * is never read.  The address ranges of Z and of X, Y (first to last element)
+ * may not overlap.  Everything else is as for the square calls, which are
+ * these with m = k = n = ldx = ldy = ldz.
+ */
+size_t afmm_workspace_size_ex(afmm_case c, int64_t m, int64_t k, int64_t n, afmm_mode mode);
+
+afmm_status afmm_multiply_caseA_ex(int64_t m, int64_t k, int64_t n, const float *X, int64_t ldx,
+                                   const int32_t *Y, int64_t ldy, float *Z, int64_t ldz,
+                                   afmm_mode mode, void *workspace, size_t workspace_bytes,
+                                   hipStream_t stream);
+
+afmm_status afmm_multiply_caseB_ex(int64_t m, int64_t k, int64_t n, const int32_t *X, int64_t ldx,
+                                   const float *Y, int64_t ldy, float *Z, int64_t ldz,
+                                   afmm_mode mode, void *workspace, size_t workspace_bytes,
+                                   hipStream_t stream);
+
+/* Addition count of the rectangular product: d_row_counts has m entries; the
+ * workspace needs afmm_workspace_size_ex(c, m, k, n, AFMM_MODE_STRICT) bytes. */
+afmm_status afmm_count_adds_ex(afmm_case c, int64_t m, int64_t k, int64_t n, const void *X,
+                               int64_t ldx, const void *Y, int64_t ldy, uint64_t *d_total,
+                               uint64_t *d_row_counts, uint32_t *d_flags, void *workspace,
+                               size_t workspace_bytes, hipStream_t stream);
+
 /*
  * Synchronous data check: runs the counting pass on `stream`, waits for it,
  * and returns AFMM_ERR_NEGATIVE_INT, AFMM_ERR_INT_RANGE (split mode, an

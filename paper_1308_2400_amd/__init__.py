@@ -53,6 +53,13 @@ _vp, _i64, _i32, _sz, _ci = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ct
                              ctypes.c_int)
 _SIGS = {
     "afmm_workspace_size": ([_ci, _i64, _ci], _sz),
+    "afmm_workspace_size_ex": ([_ci, _i64, _i64, _i64, _ci], _sz),
+    "afmm_multiply_caseA_ex": ([_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _ci, _vp, _sz,
+                                _vp], _ci),
+    "afmm_multiply_caseB_ex": ([_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _ci, _vp, _sz,
+                                _vp], _ci),
+    "afmm_count_adds_ex": ([_ci, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _sz,
+                            _vp], _ci),
     "afmm_multiply_caseA": ([_i64, _vp, _vp, _vp, _ci, _vp, _sz, _vp], _ci),
     "afmm_multiply_caseB": ([_i64, _vp, _vp, _vp, _ci, _vp, _sz, _vp], _ci),
     "afmm_count_adds": ([_ci, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _ci),
@@ -116,7 +123,20 @@ def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
-def _operands(case, X, Y):
+def _rows_stride(t, name):
+    """Leading dimension of a row-major 2-D view (unit column stride)."""
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D matrix")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride (row-major rows)")
+    ld = t.stride(0) if t.shape[0] > 1 else t.shape[1]
+    if ld < t.shape[1]:
+        raise ValueError(f"{name}: row stride below the row length")
+    return ld
+
+
+def _shape(case, X, Y):
+    """(case id, m, k, n, ldx, ldy) of X (m x k) times Y (k x n), row-major views."""
     torch = _torch()
     c = _case_id(case)
     xdt, ydt = (torch.float32, torch.int32) if c == CASE_A else (torch.int32, torch.float32)
@@ -125,40 +145,68 @@ def _operands(case, X, Y):
             raise ValueError(f"{name} must be a device tensor")
         if t.dtype != dt:
             raise TypeError(f"case {'AB'[c]}: {name} must be {dt}, got {t.dtype}")
-        if t.dim() != 2 or t.shape[0] != t.shape[1] or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous square matrix")
-    if X.shape != Y.shape or X.device != Y.device:
-        raise ValueError("X and Y must have the same shape and device")
-    return c, X.shape[0]
+    ldx, ldy = _rows_stride(X, "X"), _rows_stride(Y, "Y")
+    if X.shape[1] != Y.shape[0]:
+        raise ValueError(f"inner extents differ: X is {tuple(X.shape)}, Y is {tuple(Y.shape)}")
+    if X.device != Y.device:
+        raise ValueError("X and Y must be on the same device")
+    return c, X.shape[0], X.shape[1], Y.shape[1], ldx, ldy
+
+
+def _square(m, k, n, *lds):
+    return m == k == n and all(ld == n for ld in lds)
+
+
+def _operands(case, X, Y):
+    """Square contiguous operands (the calls that take n only)."""
+    c, m, k, n, ldx, ldy = _shape(case, X, Y)
+    if not _square(m, k, n, ldx, ldy):
+        raise ValueError("X and Y must be contiguous square matrices of the same size")
+    return c, n
 
 
 def workspace_size(case, n, mode="strict") -> int:
     return int(_lib.afmm_workspace_size(_case_id(case), n, _mode_id(mode)))
 
 
+def workspace_size_ex(case, m, k, n, mode="strict") -> int:
+    return int(_lib.afmm_workspace_size_ex(_case_id(case), m, k, n, _mode_id(mode)))
+
+
 def multiply(case, X, Y, mode="strict", out=None, workspace=None, config=None):
-    """Z = X . Y by AFMM (case 'A': X float32, Y int32; case 'B': X int32, Y float32)."""
+    """Z = X . Y by AFMM (case 'A': X float32, Y int32; case 'B': X int32, Y float32).
+
+    X is m x k and Y k x n, row-major device views (unit column stride, any row
+    stride); `out`, if given, an m x n float32 view of the same kind, of which only
+    the m x n elements are written.  `config` (strict mode, square contiguous
+    operands) picks the kernel configuration."""
     torch = _torch()
-    c, n = _operands(case, X, Y)
-    m = _mode_id(mode)
-    Z = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=X.device)
-    if Z.dtype != torch.float32 or tuple(Z.shape) != (n, n) or not Z.is_contiguous():
-        raise ValueError("out must be a contiguous float32 n x n tensor")
+    c, m, k, n, ldx, ldy = _shape(case, X, Y)
+    md = _mode_id(mode)
+    Z = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=X.device)
+    if Z.dtype != torch.float32 or tuple(Z.shape) != (m, n) or not Z.is_cuda:
+        raise ValueError("out must be a float32 m x n device tensor")
+    ldz = _rows_stride(Z, "out")
+    square = _square(m, k, n, ldx, ldy, ldz)
     if workspace is None:
-        need = workspace_size(c, n, m)
-        if config is not None:
+        need = workspace_size(c, n, md) if square else workspace_size_ex(c, m, k, n, md)
+        if config is not None and square:
             need = max(need, workspace_size(c, n, MODE_STRICT))
         workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
     ws, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     if config is not None:
-        if m != MODE_STRICT:
-            raise ValueError("an explicit config applies to the strict mode only")
+        if md != MODE_STRICT or not square:
+            raise ValueError("an explicit config applies to strict square contiguous products")
         cfg = _cfg(config)
         st = _lib.afmm_multiply_strict_config(c, n, X.data_ptr(), Y.data_ptr(), Z.data_ptr(),
                                               ctypes.byref(cfg), ws, wsb, _stream())
-    else:
+    elif square:
         fn = _lib.afmm_multiply_caseA if c == CASE_A else _lib.afmm_multiply_caseB
-        st = fn(n, X.data_ptr(), Y.data_ptr(), Z.data_ptr(), m, ws, wsb, _stream())
+        st = fn(n, X.data_ptr(), Y.data_ptr(), Z.data_ptr(), md, ws, wsb, _stream())
+    else:
+        fn = _lib.afmm_multiply_caseA_ex if c == CASE_A else _lib.afmm_multiply_caseB_ex
+        st = fn(m, k, n, X.data_ptr(), ldx, Y.data_ptr(), ldy, Z.data_ptr(), ldz, md, ws, wsb,
+                _stream())
     _check("multiply", st)
     return Z
 
@@ -166,14 +214,20 @@ def multiply(case, X, Y, mode="strict", out=None, workspace=None, config=None):
 def count_adds_async(case, X, Y, rows=False):
     """Queue the exact addition count; returns device tensors (total[1], flags[1], rows|None)."""
     torch = _torch()
-    c, n = _operands(case, X, Y)
+    c, m, k, n, ldx, ldy = _shape(case, X, Y)
     total = torch.empty(1, dtype=torch.uint64, device=X.device)
     flags = torch.empty(1, dtype=torch.int32, device=X.device)
-    rc = torch.empty(n, dtype=torch.uint64, device=X.device) if rows else None
-    ws = torch.empty(workspace_size(c, n), dtype=torch.uint8, device=X.device)
-    st = _lib.afmm_count_adds(c, n, X.data_ptr(), Y.data_ptr(), total.data_ptr(),
-                              rc.data_ptr() if rc is not None else None, flags.data_ptr(),
-                              ws.data_ptr(), ws.numel(), _stream())
+    rc = torch.empty(m, dtype=torch.uint64, device=X.device) if rows else None
+    rcp = rc.data_ptr() if rc is not None else None
+    if _square(m, k, n, ldx, ldy):
+        ws = torch.empty(workspace_size(c, n), dtype=torch.uint8, device=X.device)
+        st = _lib.afmm_count_adds(c, n, X.data_ptr(), Y.data_ptr(), total.data_ptr(), rcp,
+                                  flags.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    else:
+        ws = torch.empty(workspace_size_ex(c, m, k, n), dtype=torch.uint8, device=X.device)
+        st = _lib.afmm_count_adds_ex(c, m, k, n, X.data_ptr(), ldx, Y.data_ptr(), ldy,
+                                     total.data_ptr(), rcp, flags.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), _stream())
     _check("count_adds", st)
     return total, flags, rc
 

@@ -3,6 +3,7 @@
 #include "afmm.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -56,10 +57,36 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-afmm_status check_args(int64_t n, const void* X, const void* Y, const void* Z) {
-    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !Z) return AFMM_ERR_INVALID_ARG;
-    const size_t bytes = (size_t)n * (size_t)n * 4;
-    if (overlaps(Z, bytes, X, bytes) || overlaps(Z, bytes, Y, bytes)) return AFMM_ERR_ALIAS;
+// Problem shape: X is m x k with leading dimension ldx, Y k x n (ldy), Z m x n
+// (ldz), all row-major.  The square entry points are m = k = n = every ld.
+struct Shape {
+    int64_t m, k, n, ldx, ldy, ldz;
+};
+Shape square(int64_t n) { return Shape{n, n, n, n, n, n}; }
+
+constexpr int64_t kMaxLd = (int64_t)1 << 28;  // element pitch limit (byte offsets in 64 bits)
+
+bool shape_ok(const Shape& p) {
+    return p.m >= 1 && p.k >= 1 && p.n >= 1 && p.m <= AFMM_MAX_N && p.k <= AFMM_MAX_N &&
+           p.n <= AFMM_MAX_N && p.ldx >= p.k && p.ldy >= p.n && p.ldz >= p.n &&
+           p.ldx <= kMaxLd && p.ldy <= kMaxLd && p.ldz <= kMaxLd;
+}
+
+// Size the tuning table and the built-in rule are keyed by: the cube root of
+// the product of the three extents (n for a square problem).
+int64_t shape_size(const Shape& p) {
+    if (p.m == p.k && p.k == p.n) return p.n;
+    return std::max<int64_t>(1, std::llround(std::cbrt((double)p.m * (double)p.k * (double)p.n)));
+}
+
+// Bytes from the first to one past the last element of a rows x cols matrix.
+size_t extent(int64_t rows, int64_t cols, int64_t ld) { return (size_t)((rows - 1) * ld + cols) * 4; }
+
+afmm_status check_args(const Shape& p, const void* X, const void* Y, const void* Z) {
+    if (!shape_ok(p) || !X || !Y || !Z) return AFMM_ERR_INVALID_ARG;
+    const size_t zb = extent(p.m, p.n, p.ldz);
+    if (overlaps(Z, zb, X, extent(p.m, p.k, p.ldx)) || overlaps(Z, zb, Y, extent(p.k, p.n, p.ldy)))
+        return AFMM_ERR_ALIAS;
     if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) |
          reinterpret_cast<uintptr_t>(Z)) & 3)
         return AFMM_ERR_INVALID_ARG;
@@ -82,38 +109,48 @@ struct StrictLayout {
     size_t p8, xt, esc, total;
 };
 
-StrictLayout strict_layout(afmm_case c, int64_t n) {
+// Strict path: count bytes P8 [rows_pad x ldp] of the integer factor, rows
+// being the count-uniform side (case B: i < m; case A: j < n) and columns k;
+// case A also keeps its real factor transposed, Xt [round_up(k) x ldq], ldq
+// covering i < m.
+StrictLayout strict_layout(afmm_case c, const Shape& p) {
     StrictLayout L;
-    L.rows_pad = (int)round_up(n, kRowPad);
-    L.ldp = round_up(n, kKPad);
-    L.ldq = round_up(n, 64);
+    L.rows_pad = (int)round_up(c == AFMM_CASE_B ? p.m : p.n, kRowPad);
+    L.ldp = round_up(p.k, kKPad);
+    L.ldq = round_up(p.m, 64);
     Carve cv;
     L.p8 = cv.take((size_t)L.rows_pad * L.ldp);
-    L.xt = c == AFMM_CASE_A ? cv.take((size_t)round_up(n, kKPad) * L.ldq * 4) : 0;
+    L.xt = c == AFMM_CASE_A ? cv.take((size_t)round_up(p.k, kKPad) * L.ldq * 4) : 0;
     L.esc = cv.take(4);
     L.total = cv.off;
     return L;
 }
 
 struct SplitLayout {
-    int rows_pad;
-    int64_t ld;
+    int rows_real, rows_int;  // padded rows of the real-term planes and the integer plane
+    int64_t ld;               // K pitch
     size_t planes[4], total;  // three real-term planes, then the integer plane
 };
 
-SplitLayout split_layout(int64_t n) {
+// Split path: K-contiguous bfloat16 planes; the real factor's three terms
+// have one row per i (case A) or per j (case B), the integer plane the other.
+SplitLayout split_layout(afmm_case c, const Shape& p) {
     SplitLayout L;
-    L.rows_pad = split_rows_pad((int)n);
-    L.ld = round_up(n, 64);
+    L.rows_real = split_rows_pad((int)(c == AFMM_CASE_A ? p.m : p.n));
+    L.rows_int = split_rows_pad((int)(c == AFMM_CASE_A ? p.n : p.m));
+    L.ld = round_up(p.k, 64);
     Carve cv;
-    for (int p = 0; p < 4; ++p) L.planes[p] = cv.take((size_t)L.rows_pad * L.ld * 2);
+    for (int q = 0; q < 3; ++q) L.planes[q] = cv.take((size_t)L.rows_real * L.ld * 2);
+    L.planes[3] = cv.take((size_t)L.rows_int * L.ld * 2);
     L.total = cv.off;
     return L;
 }
 
 // count scratch: per-k weights, per-row counts (when the caller passes none),
 // flags and total
-size_t count_ws(int64_t n) { return 2 * (size_t)round_up(n * 8, 256) + 256 + 256; }
+size_t count_ws(const Shape& p) {
+    return (size_t)round_up(p.k * 8, 256) + (size_t)round_up(p.m * 8, 256) + 256 + 256;
+}
 
 // Workspace from the caller or from the stream-ordered allocator.
 struct Scratch {
@@ -184,47 +221,51 @@ afmm_config builtin_config(afmm_case c, int64_t n) {
     return lds_config(n);
 }
 
-afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
+afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
                        const afmm_config& cfg, void* ws, size_t ws_bytes, hipStream_t s) {
-    const StrictLayout L = strict_layout(c, n);
+    const StrictLayout L = strict_layout(c, p);
     Scratch sc;
     const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
     if (st != AFMM_OK) return st;
     uint8_t* P8 = sc.at(L.p8);
     uint32_t* esc = reinterpret_cast<uint32_t*>(sc.at(L.esc));
     StrictArgs a{};
-    a.n_r = a.n_c = a.n_k = (int)n;
+    a.n_k = (int)p.k;
     a.P8 = P8;
     a.ldp = L.ldp;
     a.Z = Z;
     a.esc = esc;
     if (c == AFMM_CASE_B) {
         // rows i carry the counts X[i,k]; lanes over j read Y[k,j]
-        AFMM_HIP(launch_pack_rows(static_cast<const int32_t*>(X), (int)n, P8, L.ldp, L.rows_pad,
-                                  esc, s));
+        AFMM_HIP(launch_pack_rows(static_cast<const int32_t*>(X), (int)p.m, (int)p.k, p.ldx, P8,
+                                  L.ldp, L.rows_pad, esc, s));
+        a.n_r = (int)p.m;
+        a.n_c = (int)p.n;
         a.P32 = static_cast<const int32_t*>(X);
-        a.p32_sr = n;
+        a.p32_sr = p.ldx;
         a.p32_sk = 1;
         a.Q = static_cast<const float*>(Y);
-        a.ldq = n;
-        a.z_sr = n;
+        a.ldq = p.ldy;
+        a.z_sr = p.ldz;
         a.z_sc = 1;
         a.trans_out = false;
         a.q_padded = false;
     } else {
         // transposed problem: rows j carry the counts Y[k,j]; lanes over i read X[i,k]
         float* Xt = reinterpret_cast<float*>(sc.at(L.xt));
-        AFMM_HIP(launch_pack_transpose(static_cast<const int32_t*>(Y), (int)n, P8, L.ldp,
-                                       L.rows_pad, esc, s));
-        AFMM_HIP(launch_transpose_f32(static_cast<const float*>(X), (int)n, Xt, L.ldq,
-                                      (int)round_up(n, kKPad), s));
+        AFMM_HIP(launch_pack_transpose(static_cast<const int32_t*>(Y), (int)p.k, (int)p.n, p.ldy,
+                                       P8, L.ldp, L.rows_pad, esc, s));
+        AFMM_HIP(launch_transpose_f32(static_cast<const float*>(X), (int)p.m, (int)p.k, p.ldx, Xt,
+                                      L.ldq, (int)round_up(p.k, kKPad), s));
+        a.n_r = (int)p.n;
+        a.n_c = (int)p.m;
         a.P32 = static_cast<const int32_t*>(Y);
         a.p32_sr = 1;
-        a.p32_sk = n;
+        a.p32_sk = p.ldy;
         a.Q = Xt;
         a.ldq = L.ldq;
         a.z_sr = 1;
-        a.z_sc = n;
+        a.z_sc = p.ldz;
         a.trans_out = true;
         a.q_padded = true;
     }
@@ -237,52 +278,77 @@ afmm_status strict_run(afmm_case c, int64_t n, const void* X, const void* Y, flo
     } else if (cfg.mapping == 2 || cfg.mapping == 3 || cfg.mapping == 0) {
         // the direct and sparse-k variants need float4-readable base rows (the
         // sparse-k one also 31-bit offsets); the LDS-panel variant takes the rest
-        const afmm_config d = cfg.mapping == 0 ? cfg : lds_config(n);
+        const afmm_config d = cfg.mapping == 0 ? cfg : lds_config(shape_size(p));
         AFMM_HIP(launch_rep_uniform(a, d.rows_per_wave, d.cols_per_lane, d.waves,
                                     d.unroll == 0 ? 1 : d.unroll,
                                     d.k_panel == 0 ? 16 : d.k_panel, s));
     } else {
-        BaseUniformArgs b{(int)n, static_cast<const float*>(X), static_cast<const int32_t*>(Y), Z};
-        AFMM_HIP(launch_base_uniform(b, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
+        return AFMM_ERR_UNSUPPORTED;  // mapping 1 is not compiled (config_ok rejects it)
     }
     return AFMM_OK;
 }
 
-afmm_status split_run(afmm_case c, int64_t n, const void* X, const void* Y, float* Z, void* ws,
-                      size_t ws_bytes, hipStream_t s) {
-    const SplitLayout L = split_layout(n);
+afmm_status split_run(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
+                      void* ws, size_t ws_bytes, hipStream_t s) {
+    const SplitLayout L = split_layout(c, p);
     Scratch sc;
     const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
     if (st != AFMM_OK) return st;
     uint16_t* P[4];
-    for (int p = 0; p < 4; ++p) P[p] = reinterpret_cast<uint16_t*>(sc.at(L.planes[p]));
+    for (int q = 0; q < 4; ++q) P[q] = reinterpret_cast<uint16_t*>(sc.at(L.planes[q]));
+    const int m = (int)p.m, k = (int)p.k, n = (int)p.n;
     if (c == AFMM_CASE_A) {
         // A operand: X's three terms [i][k]; B operand: Y as bf16 turned to [j][k]
-        AFMM_HIP(launch_split_real(static_cast<const float*>(X), (int)n, false, P[0], P[1], P[2],
-                                   L.ld, L.rows_pad, s));
-        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(Y), (int)n, true, P[3], L.ld,
-                                    L.rows_pad, s));
-        AFMM_HIP(launch_gemm_bf16x3((int)n, P[0], P[1], P[2], P[3], P[3], P[3], L.ld, Z, s));
+        AFMM_HIP(launch_split_real(static_cast<const float*>(X), m, k, p.ldx, false, P[0], P[1],
+                                   P[2], L.ld, L.rows_real, s));
+        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(Y), k, n, p.ldy, true, P[3], L.ld,
+                                    L.rows_int, s));
+        AFMM_HIP(launch_gemm_bf16x3(m, n, P[0], P[1], P[2], P[3], P[3], P[3], L.ld, Z, p.ldz, s));
     } else {
         // A operand: X as bf16 [i][k]; B operand: Y's three terms turned to [j][k]
-        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(X), (int)n, false, P[3], L.ld,
-                                    L.rows_pad, s));
-        AFMM_HIP(launch_split_real(static_cast<const float*>(Y), (int)n, true, P[0], P[1], P[2],
-                                   L.ld, L.rows_pad, s));
-        AFMM_HIP(launch_gemm_bf16x3((int)n, P[3], P[3], P[3], P[0], P[1], P[2], L.ld, Z, s));
+        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(X), m, k, p.ldx, false, P[3], L.ld,
+                                    L.rows_int, s));
+        AFMM_HIP(launch_split_real(static_cast<const float*>(Y), k, n, p.ldy, true, P[0], P[1],
+                                   P[2], L.ld, L.rows_real, s));
+        AFMM_HIP(launch_gemm_bf16x3(m, n, P[3], P[3], P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
     }
     return AFMM_OK;
 }
 
-afmm_status multiply(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
+size_t workspace_for(afmm_case c, const Shape& p, afmm_mode mode) {
+    if (mode == AFMM_MODE_SPLIT_BF16X3) return split_layout(c, p).total;
+    return std::max(strict_layout(c, p).total, count_ws(p));
+}
+
+afmm_status multiply(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
                      afmm_mode mode, void* ws, size_t ws_bytes, hipStream_t s) {
-    afmm_status st = check_args(n, X, Y, Z);
+    afmm_status st = check_args(p, X, Y, Z);
     if (st != AFMM_OK) return st;
     if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;
     if ((st = check_device()) != AFMM_OK) return st;
-    if (mode == AFMM_MODE_STRICT) return strict_run(c, n, X, Y, Z, afmm_default_config(c, n), ws,
-                                                    ws_bytes, s);
-    return split_run(c, n, X, Y, Z, ws, ws_bytes, s);
+    if (mode == AFMM_MODE_STRICT)
+        return strict_run(c, p, X, Y, Z, afmm_default_config(c, shape_size(p)), ws, ws_bytes, s);
+    return split_run(c, p, X, Y, Z, ws, ws_bytes, s);
+}
+
+afmm_status count_adds(afmm_case c, const Shape& p, const void* X, const void* Y,
+                       uint64_t* d_total, uint64_t* d_row_counts, uint32_t* d_flags, void* ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    if (!shape_ok(p) || !X || !Y || !d_total || (c != AFMM_CASE_A && c != AFMM_CASE_B))
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    Scratch sc;
+    if ((st = sc.get(ws, ws_bytes, count_ws(p), stream)) != AFMM_OK) return st;
+    const size_t wk_bytes = (size_t)round_up(p.k * 8, 256);
+    uint64_t* wk = reinterpret_cast<uint64_t*>(sc.at(0));
+    uint64_t* rows = d_row_counts ? d_row_counts : reinterpret_cast<uint64_t*>(sc.at(wk_bytes));
+    uint32_t* flags = d_flags ? d_flags
+                              : reinterpret_cast<uint32_t*>(
+                                    sc.at(wk_bytes + (size_t)round_up(p.m * 8, 256)));
+    AFMM_HIP(launch_count((int)c, (int)p.m, (int)p.k, (int)p.n, X, p.ldx, Y, p.ldy, wk, rows,
+                          d_total, flags, stream));
+    return AFMM_OK;
 }
 
 }  // namespace
@@ -291,37 +357,57 @@ extern "C" {
 
 size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode) {
     if (n < 1 || n > AFMM_MAX_N || (c != AFMM_CASE_A && c != AFMM_CASE_B)) return 0;
-    if (mode == AFMM_MODE_SPLIT_BF16X3) return split_layout(n).total;
-    return std::max(strict_layout(c, n).total, count_ws(n));
+    return workspace_for(c, square(n), mode);
+}
+
+size_t afmm_workspace_size_ex(afmm_case c, int64_t m, int64_t k, int64_t n, afmm_mode mode) {
+    const Shape p{m, k, n, k, n, n};
+    if (!shape_ok(p) || (c != AFMM_CASE_A && c != AFMM_CASE_B)) return 0;
+    return workspace_for(c, p, mode);
 }
 
 afmm_status afmm_multiply_caseA(int64_t n, const float* X, const int32_t* Y, float* Z,
                                 afmm_mode mode, void* workspace, size_t workspace_bytes,
                                 hipStream_t stream) {
-    return multiply(AFMM_CASE_A, n, X, Y, Z, mode, workspace, workspace_bytes, stream);
+    return multiply(AFMM_CASE_A, square(n), X, Y, Z, mode, workspace, workspace_bytes, stream);
 }
 
 afmm_status afmm_multiply_caseB(int64_t n, const int32_t* X, const float* Y, float* Z,
                                 afmm_mode mode, void* workspace, size_t workspace_bytes,
                                 hipStream_t stream) {
-    return multiply(AFMM_CASE_B, n, X, Y, Z, mode, workspace, workspace_bytes, stream);
+    return multiply(AFMM_CASE_B, square(n), X, Y, Z, mode, workspace, workspace_bytes, stream);
+}
+
+afmm_status afmm_multiply_caseA_ex(int64_t m, int64_t k, int64_t n, const float* X, int64_t ldx,
+                                   const int32_t* Y, int64_t ldy, float* Z, int64_t ldz,
+                                   afmm_mode mode, void* workspace, size_t workspace_bytes,
+                                   hipStream_t stream) {
+    return multiply(AFMM_CASE_A, Shape{m, k, n, ldx, ldy, ldz}, X, Y, Z, mode, workspace,
+                    workspace_bytes, stream);
+}
+
+afmm_status afmm_multiply_caseB_ex(int64_t m, int64_t k, int64_t n, const int32_t* X, int64_t ldx,
+                                   const float* Y, int64_t ldy, float* Z, int64_t ldz,
+                                   afmm_mode mode, void* workspace, size_t workspace_bytes,
+                                   hipStream_t stream) {
+    return multiply(AFMM_CASE_B, Shape{m, k, n, ldx, ldy, ldz}, X, Y, Z, mode, workspace,
+                    workspace_bytes, stream);
 }
 
 afmm_status afmm_count_adds(afmm_case c, int64_t n, const void* X, const void* Y,
                             uint64_t* d_total, uint64_t* d_row_counts, uint32_t* d_flags,
                             void* workspace, size_t workspace_bytes, hipStream_t stream) {
-    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !d_total || (c != AFMM_CASE_A && c != AFMM_CASE_B))
-        return AFMM_ERR_INVALID_ARG;
-    afmm_status st = check_device();
-    if (st != AFMM_OK) return st;
-    Scratch sc;
-    if ((st = sc.get(workspace, workspace_bytes, count_ws(n), stream)) != AFMM_OK) return st;
-    const size_t vec_bytes = (size_t)round_up(n * 8, 256);
-    uint64_t* wk = reinterpret_cast<uint64_t*>(sc.at(0));
-    uint64_t* rows = d_row_counts ? d_row_counts : reinterpret_cast<uint64_t*>(sc.at(vec_bytes));
-    uint32_t* flags = d_flags ? d_flags : reinterpret_cast<uint32_t*>(sc.at(2 * vec_bytes));
-    AFMM_HIP(launch_count((int)c, (int)n, X, Y, wk, rows, d_total, flags, stream));
-    return AFMM_OK;
+    if (n < 1 || n > AFMM_MAX_N) return AFMM_ERR_INVALID_ARG;
+    return count_adds(c, square(n), X, Y, d_total, d_row_counts, d_flags, workspace,
+                      workspace_bytes, stream);
+}
+
+afmm_status afmm_count_adds_ex(afmm_case c, int64_t m, int64_t k, int64_t n, const void* X,
+                               int64_t ldx, const void* Y, int64_t ldy, uint64_t* d_total,
+                               uint64_t* d_row_counts, uint32_t* d_flags, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream) {
+    return count_adds(c, Shape{m, k, n, ldx, ldy, n}, X, Y, d_total, d_row_counts, d_flags,
+                      workspace, workspace_bytes, stream);
 }
 
 afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, afmm_mode mode,
@@ -332,12 +418,12 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, 
     afmm_status st = check_device();
     if (st != AFMM_OK) return st;
     void* buf = nullptr;
-    const size_t need = count_ws(n) + 256;
-    AFMM_HIP(hipMallocAsync(&buf, need, stream));
+    const size_t cws = count_ws(square(n));
+    AFMM_HIP(hipMallocAsync(&buf, cws + 256, stream));
     uint8_t* b = static_cast<uint8_t*>(buf);
-    uint64_t* total = reinterpret_cast<uint64_t*>(b + count_ws(n));
-    uint32_t* flags = reinterpret_cast<uint32_t*>(b + count_ws(n) + 8);
-    st = afmm_count_adds(c, n, X, Y, total, nullptr, flags, b, count_ws(n), stream);
+    uint64_t* total = reinterpret_cast<uint64_t*>(b + cws);
+    uint32_t* flags = reinterpret_cast<uint32_t*>(b + cws + 8);
+    st = afmm_count_adds(c, n, X, Y, total, nullptr, flags, b, cws, stream);
     uint32_t hflags = 0;
     if (st == AFMM_OK) {
         hipError_t e = hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, stream);
@@ -370,11 +456,11 @@ afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void* X, c
                                         float* Z, const afmm_config* cfg, void* workspace,
                                         size_t workspace_bytes, hipStream_t stream) {
     if (c != AFMM_CASE_A && c != AFMM_CASE_B) return AFMM_ERR_INVALID_ARG;
-    afmm_status st = check_args(n, X, Y, Z);
+    afmm_status st = check_args(square(n), X, Y, Z);
     if (st != AFMM_OK) return st;
     if (!cfg || !config_ok(c, *cfg)) return AFMM_ERR_INVALID_ARG;
     if ((st = check_device()) != AFMM_OK) return st;
-    return strict_run(c, n, X, Y, Z, *cfg, workspace, workspace_bytes, stream);
+    return strict_run(c, square(n), X, Y, Z, *cfg, workspace, workspace_bytes, stream);
 }
 
 afmm_status afmm_set_tuning(int32_t count, const int32_t* cases, const int64_t* n_lo,

@@ -61,14 +61,17 @@ void set_last_hip_error(int e);
 
 // prep.hip
 // Both clear *esc first and set it when some count byte is 255.
-hipError_t launch_pack_rows(const int32_t* I, int n, uint8_t* P8, int64_t ldp, int rows_pad,
-                            uint32_t* esc, hipStream_t s);
-hipError_t launch_pack_transpose(const int32_t* I, int n, uint8_t* P8, int64_t ldp,
-                                 int rows_pad, uint32_t* esc, hipStream_t s);
-hipError_t launch_transpose_f32(const float* X, int n, float* Xt, int64_t ldq, int rows_pad,
-                                hipStream_t s);
-hipError_t launch_count(int case_id, int n, const void* X, const void* Y, uint64_t* wk,
-                        uint64_t* rows, uint64_t* total, uint32_t* flags, hipStream_t s);
+// I / X: rows x cols with leading dimension ldi / ldx.
+hipError_t launch_pack_rows(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
+                            int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s);
+hipError_t launch_pack_transpose(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
+                                 int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s);
+hipError_t launch_transpose_f32(const float* X, int rows, int cols, int64_t ldx, float* Xt,
+                                int64_t ldq, int rows_pad, hipStream_t s);
+// X: m x kd (ldx), Y: kd x n (ldy); wk: kd entries, rows: m entries.
+hipError_t launch_count(int case_id, int m, int kd, int n, const void* X, int64_t ldx,
+                        const void* Y, int64_t ldy, uint64_t* wk, uint64_t* rows, uint64_t* total,
+                        uint32_t* flags, hipStream_t s);
 
 // strict.hip
 struct StrictArgs {
@@ -102,14 +105,17 @@ struct BaseUniformArgs {
 hipError_t launch_base_uniform(const BaseUniformArgs& a, int R, int C, int W, hipStream_t s);
 bool base_uniform_supported(int R, int C, int W);
 
-// split.hip
-hipError_t launch_split_real(const float* R, int n, bool transpose, uint16_t* hi, uint16_t* mid,
-                             uint16_t* lo, int64_t ld, int rows_pad, hipStream_t s);
-hipError_t launch_int_to_bf16(const int32_t* I, int n, bool transpose, uint16_t* out, int64_t ld,
-                              int rows_pad, hipStream_t s);
-hipError_t launch_gemm_bf16x3(int n, const uint16_t* A0, const uint16_t* A1, const uint16_t* A2,
-                              const uint16_t* B0, const uint16_t* B1, const uint16_t* B2,
-                              int64_t ld, float* Z, hipStream_t s);
+// split.hip.  R / I: rows x cols with leading dimension ldr / ldi; planes
+// [rows_pad x ld] bfloat16, K-contiguous.
+hipError_t launch_split_real(const float* R, int rows, int cols, int64_t ldr, bool transpose,
+                             uint16_t* hi, uint16_t* mid, uint16_t* lo, int64_t ld, int rows_pad,
+                             hipStream_t s);
+hipError_t launch_int_to_bf16(const int32_t* I, int rows, int cols, int64_t ldi, bool transpose,
+                              uint16_t* out, int64_t ld, int rows_pad, hipStream_t s);
+hipError_t launch_gemm_bf16x3(int M, int N, const uint16_t* A0, const uint16_t* A1,
+                              const uint16_t* A2, const uint16_t* B0, const uint16_t* B1,
+                              const uint16_t* B2, int64_t ld, float* Z, int64_t ldz,
+                              hipStream_t s);
 int split_rows_pad(int n);
 
 }  // namespace afmm

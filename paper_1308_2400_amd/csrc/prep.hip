@@ -12,11 +12,12 @@
 namespace afmm {
 
 // ---------------------------------------------------------------------------
-// P8[r][k] = count_byte(I[r][k]) for r, k < n; zero on the padding.
-// One thread per output dword (4 counts).
+// P8[r][k] = count_byte(I[r * ldi + k]) for r < rows, k < cols; zero on the
+// padding.  One thread per output dword (4 counts).
 __global__ void zero_u32_kernel(uint32_t* w) { *w = 0; }
 
-__global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restrict__ I, int n,
+__global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restrict__ I, int rows,
+                                                       int cols, int64_t ldi,
                                                        uint8_t* __restrict__ P8, int64_t ldp,
                                                        int rows_pad, uint32_t* __restrict__ esc) {
     bool hit = false;
@@ -27,11 +28,11 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restric
         const int64_t r = w / words_per_row;
         const int64_t k = (w - r * words_per_row) * 4;
         uint32_t word = 0;
-        if (r < n) {
-            const int32_t* src = I + r * n;
+        if (r < rows) {
+            const int32_t* src = I + r * ldi;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-                if (k + t < n) {
+                if (k + t < cols) {
                     const uint32_t c = count_byte(src[k + t]);
                     hit |= c == 255u;
                     word |= c << (8 * t);
@@ -42,8 +43,10 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restric
     if (hit) atomicOr(esc, 1u);
 }
 
-// P8[j][k] = count_byte(I[k][j]): 64 x 64 tiles through LDS.  Block (64, 4).
-__global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __restrict__ I, int n,
+// P8[j][k] = count_byte(I[k * ldi + j]) for k < rows, j < cols (I is rows x
+// cols): 64 x 64 tiles through LDS.  Block (64, 4).
+__global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __restrict__ I, int rows,
+                                                            int cols, int64_t ldi,
                                                             uint8_t* __restrict__ P8,
                                                             int64_t ldp, uint32_t* __restrict__ esc) {
     __shared__ uint8_t tile[64][64 + 4];
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __re
     const int tx = threadIdx.x, ty = threadIdx.y;
     for (int kr = ty; kr < 64; kr += 4) {
         const int k = k0 + kr, j = j0 + tx;
-        const uint32_t c = (k < n && j < n) ? count_byte(I[(int64_t)k * n + j]) : 0u;
+        const uint32_t c = (k < rows && j < cols) ? count_byte(I[(int64_t)k * ldi + j]) : 0u;
         hit |= c == 255u;
         tile[kr][tx] = (uint8_t)c;
     }
@@ -69,43 +72,47 @@ __global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __re
     }
 }
 
-// Xt[k][i] = X[i][k] for i, k < n; zero on the padding.  Block (64, 4).
-__global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restrict__ X, int n,
+// Xt[k][i] = X[i * ldx + k] for i < rows, k < cols; zero on the padding.
+// Block (64, 4).
+__global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restrict__ X, int rows,
+                                                           int cols, int64_t ldx,
                                                            float* __restrict__ Xt, int64_t ldq) {
     __shared__ float tile[64][64 + 1];
     const int i0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
     const int tx = threadIdx.x, ty = threadIdx.y;
     for (int ir = ty; ir < 64; ir += 4) {
         const int i = i0 + ir, k = k0 + tx;
-        tile[ir][tx] = (i < n && k < n) ? X[(int64_t)i * n + k] : 0.0f;
+        tile[ir][tx] = (i < rows && k < cols) ? X[(int64_t)i * ldx + k] : 0.0f;
     }
     __syncthreads();
     for (int kr = ty; kr < 64; kr += 4) Xt[(int64_t)(k0 + kr) * ldq + i0 + tx] = tile[tx][kr];
 }
 
-hipError_t launch_pack_rows(const int32_t* I, int n, uint8_t* P8, int64_t ldp, int rows_pad,
-                            uint32_t* esc, hipStream_t s) {
+hipError_t launch_pack_rows(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
+                            int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s) {
     const int64_t words = (int64_t)rows_pad * (ldp / 4);
     const int grid = (int)std::min<int64_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
-    hipLaunchKernelGGL(pack_rows_kernel, dim3(grid), dim3(256), 0, s, I, n, P8, ldp, rows_pad,
+    hipLaunchKernelGGL(pack_rows_kernel, dim3(grid), dim3(256), 0, s, I, rows, cols, ldi, P8, ldp,
+                       rows_pad, esc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_transpose(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
+                                 int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s) {
+    // P8 has rows_pad rows (j, from I's columns) and ldp columns (k, from I's rows)
+    dim3 grid(rows_pad / 64, (unsigned)(ldp / 64));
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
+    hipLaunchKernelGGL(pack_transpose_kernel, grid, dim3(64, 4), 0, s, I, rows, cols, ldi, P8, ldp,
                        esc);
     return hipGetLastError();
 }
 
-hipError_t launch_pack_transpose(const int32_t* I, int n, uint8_t* P8, int64_t ldp,
-                                 int rows_pad, uint32_t* esc, hipStream_t s) {
-    dim3 grid(rows_pad / 64, (unsigned)(ldp / 64));
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
-    hipLaunchKernelGGL(pack_transpose_kernel, grid, dim3(64, 4), 0, s, I, n, P8, ldp, esc);
-    return hipGetLastError();
-}
-
-hipError_t launch_transpose_f32(const float* X, int n, float* Xt, int64_t ldq, int rows_pad,
-                                hipStream_t s) {
+hipError_t launch_transpose_f32(const float* X, int rows, int cols, int64_t ldx, float* Xt,
+                                int64_t ldq, int rows_pad, hipStream_t s) {
     // Xt has rows_pad rows (k) and ldq columns (i); both multiples of 64.
     dim3 grid((unsigned)(ldq / 64), rows_pad / 64);
-    hipLaunchKernelGGL(transpose_f32_kernel, grid, dim3(64, 4), 0, s, X, n, Xt, ldq);
+    hipLaunchKernelGGL(transpose_f32_kernel, grid, dim3(64, 4), 0, s, X, rows, cols, ldx, Xt, ldq);
     return hipGetLastError();
 }
 
@@ -175,12 +182,12 @@ __device__ __forceinline__ void for_row(const uint32_t* __restrict__ row, int n,
 // wk[k] = weight of row k of the post-factor Y:
 //   case A: sum_j max(Y[k,j], 0)     (Y integer; < n * 2^31, no overflow)
 //   case B: #{j : Y[k,j] != 0}       (Y real)
-__global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, bool vec,
+__global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, int64_t ldy, bool vec,
                                                          const void* __restrict__ Yv,
                                                          uint64_t* __restrict__ wk,
                                                          uint32_t* __restrict__ flags) {
     const int k = blockIdx.x;
-    const uint32_t* y = (const uint32_t*)Yv + (int64_t)k * n;
+    const uint32_t* y = (const uint32_t*)Yv + (int64_t)k * ldy;
     uint64_t s = 0;
     uint32_t fl = 0;
     if (case_id == 0) {
@@ -206,13 +213,13 @@ __global__ __launch_bounds__(256) void count_kstat_kernel(int case_id, int n, bo
 // No row sum can overflow 64 bits for n <= 2^16: a case-A weight is below
 // n * 2^31 <= 2^47, a case-B term below 2^31 * n <= 2^47, and a row has at most
 // 2^16 terms.  Only the total over rows can; count_total_kernel saturates it.
-__global__ __launch_bounds__(256) void count_rows_kernel(int case_id, int n, bool vec,
+__global__ __launch_bounds__(256) void count_rows_kernel(int case_id, int n, int64_t ldx, bool vec,
                                                         const void* __restrict__ Xv,
                                                         const uint64_t* __restrict__ wk,
                                                         uint64_t* __restrict__ rows,
                                                         uint32_t* __restrict__ flags) {
     const int i = blockIdx.x;
-    const uint32_t* x = (const uint32_t*)Xv + (int64_t)i * n;
+    const uint32_t* x = (const uint32_t*)Xv + (int64_t)i * ldx;
     uint64_t s = 0;
     uint32_t fl = 0;
     if (case_id == 0) {
@@ -250,17 +257,20 @@ __global__ __launch_bounds__(256) void count_total_kernel(int n, const uint64_t*
     }
 }
 
-hipError_t launch_count(int case_id, int n, const void* X, const void* Y, uint64_t* wk,
-                        uint64_t* rows, uint64_t* total, uint32_t* flags, hipStream_t s) {
-    // rows: n entries (the caller's per-row output or scratch)
+hipError_t launch_count(int case_id, int m, int kd, int n, const void* X, int64_t ldx,
+                        const void* Y, int64_t ldy, uint64_t* wk, uint64_t* rows, uint64_t* total,
+                        uint32_t* flags, hipStream_t s) {
+    // X is m x kd, Y kd x n; wk: kd entries; rows: m entries (the caller's
+    // per-row output or scratch)
     hipLaunchKernelGGL(count_zero_kernel, dim3(1), dim3(1), 0, s, total, flags);
     // 16-byte row loads need every row start 16-byte aligned
-    const bool vy = n % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
-    const bool vx = n % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
-    hipLaunchKernelGGL(count_kstat_kernel, dim3(n), dim3(256), 0, s, case_id, n, vy, Y, wk, flags);
-    hipLaunchKernelGGL(count_rows_kernel, dim3(n), dim3(256), 0, s, case_id, n, vx, X, wk, rows,
+    const bool vy = n % 4 == 0 && ldy % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
+    const bool vx = kd % 4 == 0 && ldx % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    hipLaunchKernelGGL(count_kstat_kernel, dim3(kd), dim3(256), 0, s, case_id, n, ldy, vy, Y, wk,
                        flags);
-    hipLaunchKernelGGL(count_total_kernel, dim3(1), dim3(256), 0, s, n, rows, total, flags);
+    hipLaunchKernelGGL(count_rows_kernel, dim3(m), dim3(256), 0, s, case_id, kd, ldx, vx, X, wk,
+                       rows, flags);
+    hipLaunchKernelGGL(count_total_kernel, dim3(1), dim3(256), 0, s, m, rows, total, flags);
     return hipGetLastError();
 }
 

@@ -172,11 +172,10 @@ __device__ __forceinline__ void rep_sparse_tile(
     // panel p -> LDS buffer p & 1
 #define AFMM_SPARSE_ISSUE(p)                                                                  \
     do {                                                                                      \
-        const int k0_ = (p) * KP;                                                             \
-        const int rows_ = n_k - k0_; /* > 0 for every issued panel */                         \
+        const int k0_ = (p) * KP; /* < n_k for every issued panel */                          \
         const __amdgpu_buffer_rsrc_t rsrc_ = __builtin_amdgcn_make_buffer_rsrc(               \
-            const_cast<float*>(Q + (int64_t)k0_ * ldq), (short)0, (int)(rows_ * ldq * 4),     \
-            0x00020000);                                                                      \
+            const_cast<float*>(Q + (int64_t)k0_ * ldq), (short)0,                             \
+            base_records(n_k, k0_, ldq, n_c), 0x00020000);                                    \
         float* dst_ = lds + ((p) & 1) * (KP * TN);                                            \
         _Pragma("unroll") for (int s = 0; s < CPW; ++s)                                       \
             __builtin_amdgcn_raw_ptr_buffer_load_lds(                                         \

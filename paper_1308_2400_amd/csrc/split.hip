@@ -42,10 +42,12 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
     return __uint_as_float((uint32_t)h << 16);
 }
 
-// out planes [rows_pad x ld] (bf16 bits).  Tile 64 x 64 through LDS, block (64, 4).
+// out planes [rows_pad x ld] (bf16 bits) from in: rows x cols with leading
+// dimension ldi (zero outside).  Tile 64 x 64 through LDS, block (64, 4).
 // TRANS: out[c][r] = f(in[r][c]); else out[r][c] = f(in[r][c]).
 template <bool TRANS>
-__global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict__ in, int n,
+__global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict__ in, int rows,
+                                                        int cols, int64_t ldi,
                                                         uint16_t* __restrict__ hi,
                                                         uint16_t* __restrict__ mid,
                                                         uint16_t* __restrict__ lo, int64_t ld) {
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict
         // TRANS: read in[c0 + t][o0 + tx] (coalesced), keep at tile[tx][t]
         const int r = TRANS ? c0 + t : o0 + t;
         const int c = TRANS ? o0 + tx : c0 + tx;
-        const float v = (r < n && c < n) ? in[(int64_t)r * n + c] : 0.0f;
+        const float v = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : 0.0f;
         if (TRANS) tile[tx][t] = v; else tile[t][tx] = v;
     }
     __syncthreads();
@@ -75,7 +77,8 @@ __global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict__ in, int n,
+__global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict__ in, int rows,
+                                                      int cols, int64_t ldi,
                                                       uint16_t* __restrict__ out, int64_t ld) {
     __shared__ int32_t tile[64][65];
     const int o0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict
     for (int t = ty; t < 64; t += 4) {
         const int r = TRANS ? c0 + t : o0 + t;
         const int c = TRANS ? o0 + tx : c0 + tx;
-        const int32_t v = (r < n && c < n) ? in[(int64_t)r * n + c] : 0;
+        const int32_t v = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : 0;
         if (TRANS) tile[tx][t] = v; else tile[t][tx] = v;
     }
     __syncthreads();
@@ -94,23 +97,28 @@ __global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict
     }
 }
 
-hipError_t launch_split_real(const float* R, int n, bool transpose, uint16_t* hi, uint16_t* mid,
-                             uint16_t* lo, int64_t ld, int rows_pad, hipStream_t s) {
+hipError_t launch_split_real(const float* R, int rows, int cols, int64_t ldr, bool transpose,
+                             uint16_t* hi, uint16_t* mid, uint16_t* lo, int64_t ld, int rows_pad,
+                             hipStream_t s) {
     dim3 grid(rows_pad / 64, (unsigned)(ld / 64));
     if (transpose)
-        hipLaunchKernelGGL(split_real_kernel<true>, grid, dim3(64, 4), 0, s, R, n, hi, mid, lo, ld);
+        hipLaunchKernelGGL(split_real_kernel<true>, grid, dim3(64, 4), 0, s, R, rows, cols, ldr, hi,
+                           mid, lo, ld);
     else
-        hipLaunchKernelGGL(split_real_kernel<false>, grid, dim3(64, 4), 0, s, R, n, hi, mid, lo, ld);
+        hipLaunchKernelGGL(split_real_kernel<false>, grid, dim3(64, 4), 0, s, R, rows, cols, ldr,
+                           hi, mid, lo, ld);
     return hipGetLastError();
 }
 
-hipError_t launch_int_to_bf16(const int32_t* I, int n, bool transpose, uint16_t* out, int64_t ld,
-                              int rows_pad, hipStream_t s) {
+hipError_t launch_int_to_bf16(const int32_t* I, int rows, int cols, int64_t ldi, bool transpose,
+                              uint16_t* out, int64_t ld, int rows_pad, hipStream_t s) {
     dim3 grid(rows_pad / 64, (unsigned)(ld / 64));
     if (transpose)
-        hipLaunchKernelGGL(int_bf16_kernel<true>, grid, dim3(64, 4), 0, s, I, n, out, ld);
+        hipLaunchKernelGGL(int_bf16_kernel<true>, grid, dim3(64, 4), 0, s, I, rows, cols, ldi, out,
+                           ld);
     else
-        hipLaunchKernelGGL(int_bf16_kernel<false>, grid, dim3(64, 4), 0, s, I, n, out, ld);
+        hipLaunchKernelGGL(int_bf16_kernel<false>, grid, dim3(64, 4), 0, s, I, rows, cols, ldi, out,
+                           ld);
     return hipGetLastError();
 }
 
@@ -141,10 +149,10 @@ __device__ __forceinline__ void gemm_tile_coords(int t, int tiles_m, int tiles_n
 
 template <bool TRIPLE_A>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
-    int n, const uint16_t* __restrict__ A0, const uint16_t* __restrict__ A1,
+    int M, int N, const uint16_t* __restrict__ A0, const uint16_t* __restrict__ A1,
     const uint16_t* __restrict__ A2, const uint16_t* __restrict__ B0,
     const uint16_t* __restrict__ B1, const uint16_t* __restrict__ B2, int64_t ld,
-    float* __restrict__ Z, int tiles_m, int tiles_n) {
+    float* __restrict__ Z, int64_t ldz, int tiles_m, int tiles_n) {
     // LDS stage: planes 0..2 = the split side (hi, mid, lo), plane 3 = the other side
     constexpr int STAGE = 4 * kPlane;
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * STAGE];
@@ -258,22 +266,24 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
             for (int v = 0; v < 16; ++v) {
                 const int row = m0 + wm + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
                 const int col = c0 + wc + j * 32 + (lane & 31);
-                if (row < n && col < n) Z[(int64_t)row * n + col] = acc_hi[i][j][v] + acc_lo[i][j][v];
+                if (row < M && col < N) Z[(int64_t)row * ldz + col] = acc_hi[i][j][v] + acc_lo[i][j][v];
             }
 }
 
-hipError_t launch_gemm_bf16x3(int n, const uint16_t* A0, const uint16_t* A1, const uint16_t* A2,
-                              const uint16_t* B0, const uint16_t* B1, const uint16_t* B2,
-                              int64_t ld, float* Z, hipStream_t s) {
-    const int tiles_m = (n + kGM - 1) / kGM, tiles_n = (n + kGN - 1) / kGN;
+hipError_t launch_gemm_bf16x3(int M, int N, const uint16_t* A0, const uint16_t* A1,
+                              const uint16_t* A2, const uint16_t* B0, const uint16_t* B1,
+                              const uint16_t* B2, int64_t ld, float* Z, int64_t ldz,
+                              hipStream_t s) {
+    // A planes: split_rows_pad(M) rows, B planes: split_rows_pad(N) rows, K pitch ld
+    const int tiles_m = (M + kGM - 1) / kGM, tiles_n = (N + kGN - 1) / kGN;
     const int n_tiles = tiles_m * tiles_n;
     const bool triple_a = A0 != A1;
     if (triple_a)
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(256), 0, s, n, A0, A1, A2,
-                           B0, B1, B2, ld, Z, tiles_m, tiles_n);
+        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(256), 0, s, M, N, A0, A1,
+                           A2, B0, B1, B2, ld, Z, ldz, tiles_m, tiles_n);
     else
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(256), 0, s, n, A0, A1,
-                           A2, B0, B1, B2, ld, Z, tiles_m, tiles_n);
+        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(256), 0, s, M, N, A0,
+                           A1, A2, B0, B1, B2, ld, Z, ldz, tiles_m, tiles_n);
     return hipGetLastError();
 }
 

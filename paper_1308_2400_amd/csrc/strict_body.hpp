@@ -86,19 +86,27 @@ __device__ __forceinline__ void panel_load(float4* buf,
     }
 }
 
+// Bytes of the base rows [k0, n_k) a buffer resource may cover: whole rows of
+// pitch ldq, except that the last row ends at its n_c-th element (the caller
+// may own no more than that).
+__device__ __forceinline__ int base_records(int n_k, int k0, int64_t ldq, int n_c) {
+    const int rows = n_k - k0;
+    return rows > 0 ? (int)(((int64_t)(rows - 1) * ldq + n_c) * 4) : 0;
+}
+
 // Same with a buffer resource covering the base rows from k0 on: the
 // per-thread offsets are fixed, the panel start moves in scalar registers, and
-// rows past the end (or bytes past num_records) read as zero instead of
-// faulting.  Columns past n_c read neighbouring data; those lanes are never
-// stored, and rows past n_k have zero counts, so neither value is used.
+// reads past the resource's end read as zero instead of faulting.  Columns
+// past n_c read neighbouring data (or zero); those lanes are never stored, and
+// rows past n_k have zero counts, so neither value is used.
 template <int R, int C, int W, int KP>
 __device__ __forceinline__ void panel_load_buf(float4* buf, const float* __restrict__ Q,
-                                               int64_t ldq, int n_k, int k0,
+                                               int64_t ldq, int n_k, int n_c, int k0,
                                                const uint32_t* voff) {
     using T = RepTile<R, C, W, KP>;
-    const int rows = n_k - k0 > 0 ? n_k - k0 : 0;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(Q + (int64_t)k0 * ldq), (short)0, (int)(rows * ldq * 4), 0x00020000);
+        const_cast<float*>(Q + (int64_t)k0 * ldq), (short)0, base_records(n_k, k0, ldq, n_c),
+        0x00020000);
 #pragma unroll
     for (int s = 0; s < T::F4T; ++s) {
         const int e = threadIdx.x + s * W * kWave;
@@ -193,7 +201,7 @@ __device__ __forceinline__ void rep_uniform_tile(
         const int e = threadIdx.x + s * W * kWave;
         voff[s] = (uint32_t)(((e / (TN / 4)) * ldq + c0 + (e % (TN / 4)) * 4) * 4);
     }
-    if (BUF) panel_load_buf<R, C, W, KP>(stage, Q, ldq, n_k, 0, voff);
+    if (BUF) panel_load_buf<R, C, W, KP>(stage, Q, ldq, n_k, n_c, 0, voff);
     else panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, 0, c0);
     panel_store<R, C, W, KP>(stage, lds);
     // counts of the first panel: 16 bytes per row (scalar loads)
@@ -207,7 +215,7 @@ __device__ __forceinline__ void rep_uniform_tile(
         const float* pan = lds + (p & 1) * (KP * TN);
         const bool more = p + 1 < n_panels;
         if (more) {
-            if (BUF) panel_load_buf<R, C, W, KP>(stage, Q, ldq, n_k, k0 + KP, voff);
+            if (BUF) panel_load_buf<R, C, W, KP>(stage, Q, ldq, n_k, n_c, k0 + KP, voff);
             else panel_load<R, C, W, KP, VEC>(stage, Q, ldq, n_k, n_c, k0 + KP, c0);
         }
 

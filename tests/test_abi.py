@@ -74,6 +74,36 @@ def test_argument_errors_on_host(afmm):
     assert afmm.afmm_count_adds(0, 8, 16, 4096, None, None, None, None, 0, None) == 1
 
 
+def test_rectangular_argument_errors_on_host(afmm):
+    fA, fB = afmm.afmm_multiply_caseA_ex, afmm.afmm_multiply_caseB_ex
+    X, Y, Z = 4096, 1 << 20, 1 << 24
+    # extents below 1, leading dimensions below the row length, null pointers
+    assert fB(0, 4, 4, X, 4, Y, 4, Z, 4, 0, None, 0, None) == 1
+    assert fB(4, 4, 0, X, 4, Y, 4, Z, 4, 0, None, 0, None) == 1
+    assert fB(4, 8, 4, X, 7, Y, 4, Z, 4, 0, None, 0, None) == 1
+    assert fB(4, 8, 6, X, 8, Y, 5, Z, 6, 0, None, 0, None) == 1
+    assert fA(4, 8, 6, X, 8, Y, 6, Z, 5, 0, None, 0, None) == 1
+    assert fA(4, 8, 6, None, 8, Y, 6, Z, 6, 0, None, 0, None) == 1
+    assert fA(70000, 8, 6, X, 8, Y, 6, Z, 6, 0, None, 0, None) == 1
+    # Z's range (m-1)*ldz + n elements overlaps X's (m-1)*ldx + k
+    assert fA(3, 5, 2, X, 100, Y, 2, X + 4 * 150, 2, 0, None, 0, None) == 2
+    assert fA(3, 5, 2, X, 5, Y, 2, X + 4 * 15, 2, 0, None, 0, None) != 2
+    # counting: bad leading dimension
+    assert afmm.afmm_count_adds_ex(1, 4, 8, 6, X, 7, Y, 6, Z, None, None, None, 0, None) == 1
+
+
+def test_rectangular_workspace_sizes(afmm):
+    for case in (0, 1):
+        for (m, k, n) in [(1, 1, 1), (5, 700, 3), (300, 2, 900)]:
+            s = afmm.afmm_workspace_size_ex(case, m, k, n, 0)
+            rows = n if case == 0 else m
+            assert s >= ((rows + 63) // 64 * 64) * ((k + 63) // 64 * 64)
+            assert s >= 8 * (m + k)
+            assert afmm.afmm_workspace_size_ex(case, m, k, n, 1) >= 2 * 4 * (m + n) * k
+        assert afmm.afmm_workspace_size_ex(case, 64, 64, 64, 0) == afmm.afmm_workspace_size(case, 64, 0)
+    assert afmm.afmm_workspace_size_ex(0, 0, 4, 4, 0) == 0
+
+
 def test_config_table(afmm):
     assert afmm.config_supported("B", (0, 8, 8, 8))
     assert afmm.config_supported("A", (0, 4, 4, 4))

@@ -1,0 +1,164 @@
+"""Rectangular (m x k times k x n) and strided products on the GPU against the oracle.
+
+Strict results bit-identical to the oracle's loops with separate i, k, j bounds; the
+split form within 1e-6 of the binary64 product; counts exact.  Operands are row-major
+views whose padding holds values that would show if they were read (NaN reals,
+out-of-range integers), and the padding of Z must keep its contents.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    import paper_1308_2400_amd  # noqa: F401
+    return torch.device("cuda:0")
+
+
+def _afmm():
+    import paper_1308_2400_amd
+    return paper_1308_2400_amd
+
+
+def _rect(case, m, k, n, seed, int_hi=7, d_real=0.6, d_int=0.7):
+    r = np.random.default_rng(seed)
+    real_shape, int_shape = ((m, k), (k, n)) if case == "A" else ((k, n), (m, k))
+    real = r.standard_normal(real_shape).astype(np.float32)
+    real[r.random(real_shape) > d_real] = 0
+    ints = r.integers(0, int_hi + 1, int_shape).astype(np.int32)
+    ints[r.random(int_shape) > d_int] = 0
+    return (real, ints) if case == "A" else (ints, real)
+
+
+def _padded(dev, a, extra, fill):
+    """A device view of `a` inside a wider buffer (row stride = cols + extra)."""
+    import torch
+    rows, cols = a.shape
+    buf = np.full((rows, cols + extra), fill, dtype=a.dtype)
+    buf[:, :cols] = a
+    t = torch.from_numpy(buf).to(dev)
+    return t[:, :cols]
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+SHAPES = [(1, 1, 1), (1, 300, 7), (7, 1, 300), (300, 7, 1), (65, 129, 63), (200, 57, 333),
+          (513, 100, 70), (33, 700, 190)]
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("shape", SHAPES, ids=str)
+def test_rect_strict_bitexact(dev, case, shape):
+    import torch
+    m, k, n = shape
+    X, Y = _rect(case, m, k, n, m * 7 + k * 3 + n)
+    afmm = _afmm()
+    Z = afmm.multiply(case, torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)).cpu().numpy()
+    Zr, _ = oracle.strict_f32(case, X, Y)
+    assert Z.shape == (m, n)
+    assert np.array_equal(_bits(Z), _bits(Zr))
+
+
+CFGS = [(0, 4, 16, 16, 1, 16), (0, 2, 1, 4, 1, 16), (0, 4, 2, 4, 2, 16), (2, 8, 8, 4),
+        (3, 2, 16, 16, 1, 8), (3, 2, 8, 16, 2, 16), (3, 1, 16, 16, 1, 8)]
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("cfg", CFGS, ids=str)
+def test_rect_strict_every_mapping(dev, case, cfg):
+    """Each kernel form on tall, wide and long-k shapes (chosen through a tuning table
+    that covers every size), strided operands."""
+    import torch
+    afmm = _afmm()
+    try:
+        afmm.set_tuning([(case, 1, 1 << 30, cfg)])
+        for (m, k, n) in [(130, 40, 600), (600, 300, 20), (17, 1000, 129)]:
+            X, Y = _rect(case, m, k, n, m + k + n)
+            Xd = _padded(dev, X, 5, np.nan if case == "A" else 300)
+            # a row stride that is a multiple of 4 keeps the 16-byte-load kernels in play
+            Yd = _padded(dev, Y, 4, 300 if case == "A" else np.nan)
+            Zbuf = torch.full((m, n + 9), -3.25, dtype=torch.float32, device=dev)
+            afmm.multiply(case, Xd, Yd, out=Zbuf[:, :n])
+            Zh = Zbuf.cpu().numpy()
+            Zr, _ = oracle.strict_f32(case, X, Y)
+            assert np.array_equal(_bits(Zh[:, :n]), _bits(Zr)), (cfg, m, k, n)
+            assert (Zh[:, n:] == -3.25).all()
+    finally:
+        afmm.set_tuning([])
+        afmm.load_tuning()
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_rect_last_row_ends_the_allocation(dev, case):
+    """Y (case B) or X (case A) as a strided view whose last row ends the buffer: the
+    kernels must not read past its n-th (k-th) element."""
+    import torch
+    m, k, n, ld = 90, 75, 101, 104
+    X, Y = _rect(case, m, k, n, 3)
+    afmm = _afmm()
+    rows, cols, src = (k, n, Y) if case == "B" else (m, k, X)
+    flat = np.zeros((rows - 1) * ld + cols, dtype=src.dtype)
+    for r in range(rows):
+        flat[r * ld:r * ld + cols] = src[r]
+    buf = torch.from_numpy(flat).to(dev)
+    view = torch.as_strided(buf, (rows, cols), (ld, 1))
+    other = torch.from_numpy(X if case == "B" else Y).to(dev)
+    Xd, Yd = (other, view) if case == "B" else (view, other)
+    Z = afmm.multiply(case, Xd, Yd).cpu().numpy()
+    Zr, _ = oracle.strict_f32(case, X, Y)
+    assert np.array_equal(_bits(Z), _bits(Zr))
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (200, 57, 333), (513, 1024, 70), (96, 2000, 300)],
+                         ids=str)
+def test_rect_split_error(dev, case, shape):
+    import torch
+    m, k, n = shape
+    X, Y = _rect(case, m, k, n, 11 + m, int_hi=200)
+    afmm = _afmm()
+    Xd = _padded(dev, X, 7, np.nan if case == "A" else 999)
+    Yd = _padded(dev, Y, 1, 999 if case == "A" else np.nan)
+    Zbuf = torch.full((m, n + 4), 7.5, dtype=torch.float32, device=dev)
+    afmm.multiply(case, Xd, Yd, mode="split_bf16x3", out=Zbuf[:, :n])
+    Zh = Zbuf.cpu().numpy()
+    Z64 = oracle.product_f64(case, X, Y)
+    assert oracle.rel_frobenius(Zh[:, :n], Z64) <= 1e-6
+    assert (Zh[:, n:] == 7.5).all()
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (65, 129, 63), (300, 7, 1), (1, 300, 7),
+                                   (700, 333, 45)], ids=str)
+def test_rect_count(dev, case, shape):
+    m, k, n = shape
+    X, Y = _rect(case, m, k, n, 5 * m + n, int_hi=300)
+    afmm = _afmm()
+    Xd = _padded(dev, X, 2, np.nan if case == "A" else -5)
+    Yd = _padded(dev, Y, 6, -5 if case == "A" else np.nan)
+    total, rows, flags = afmm.count_adds(case, Xd, Yd, rows=True, with_flags=True)
+    ot, orows, ofl = oracle.count(case, X, Y)
+    assert total == ot
+    assert np.array_equal(rows.cpu().numpy(), orows)
+    assert flags == ofl
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_rect_large_sampled_rows(dev, case):
+    """A 2048 x 4096 times 4096 x 1536 product, sampled rows against the oracle."""
+    import torch
+    m, k, n = 2048, 4096, 1536
+    X, Y = _rect(case, m, k, n, 21, int_hi=5, d_real=0.5, d_int=0.4)
+    afmm = _afmm()
+    Z = afmm.multiply(case, torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)).cpu().numpy()
+    rows = [0, 1, 777, 1500, m - 1]
+    Zr, _ = oracle.strict_f32(case, X[rows], Y, rows=rows, x_rows_only=True)
+    assert np.array_equal(_bits(Z[rows]), _bits(Zr))
