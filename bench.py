@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--table1", action="store_true",
                    help="run the paper's Table 1 parameter grid (case A) instead of the benchmark")
+    p.add_argument("--c5", action="store_true",
+                   help="run the case-A n=16384 workload (strict vs split, sampled-row checks) "
+                        "instead of the benchmark")
     p.add_argument("--copy-mb", type=int, default=0,
                    help="first run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -190,6 +193,58 @@ def empirical_fit(rows):
                              "rows": len(big)}}
 
 
+def c5(args):
+    """Case A, n=16384: X U(-1,1) with d1 = 0.05, Y Geometric(0.3) clipped to 0..255: the
+    strict kernel beside the split form; strict rows bit-exact and the split's error
+    against the binary64 product on sampled rows (64 rows i = 256 t + 17 plus the rows
+    with the most and the fewest additions)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_1308_2400_amd as afmm
+    stream = torch.cuda.current_stream()
+    w = gen.caseA_n16384()
+    n = w.n
+    log("bench: generating caseA_n16384 (two 1 GiB matrices)")
+    X, Y = w.X(), w.Y()
+    Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    adds, rows = afmm.count_adds("A", Xd, Yd, rows=True)
+    rows = rows.cpu().numpy()
+    sample = sorted(set([256 * t + 17 for t in range(64)] + [int(rows.argmax()), int(rows.argmin())]))
+    steps = max(1, min(args.steps, 3))
+    Z = afmm.multiply("A", Xd, Yd)
+    strict_ms = event_time_ms(lambda: afmm.multiply("A", Xd, Yd, out=Z), steps, stream)
+    log(f"bench: c5 strict {strict_ms:.2f} ms")
+    Zs = afmm.multiply("A", Xd, Yd, mode="split_bf16x3")
+    split_ms = event_time_ms(lambda: afmm.multiply("A", Xd, Yd, mode="split_bf16x3", out=Zs),
+                             steps, stream)
+    log(f"bench: c5 split {split_ms:.2f} ms")
+    Zh, Zsh = Z.cpu().numpy()[sample], Zs.cpu().numpy()[sample]
+    Zr, _ = oracle.caseA_f32(X[sample], Y, rows=sample, x_rows_only=True)
+    Z64 = oracle.product_f64("A", X[sample], Y, rows=sample, x_rows_only=True)
+    out = {"metric": "case A n=16384 (C5): strict AFMM vs split-BF16x3", "unit": "ms",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded generator)",
+           "dtype": "f32", "config": {"workload": w.name, "case": "A", "n": n, "d1": 0.05,
+                                      "int_dist": "Geometric(0.3) clipped to [0,255]",
+                                      "real_dist": "U(-1,1)"},
+           "useful_adds": adds,
+           "strict": {"ms": strict_ms, "useful_adds_per_s": adds / (strict_ms * 1e-3),
+                      "frac_of_add_peak": adds / (strict_ms * 1e-3) / 1e12 / PEAK_ADD_TFLOPS,
+                      "bitexact_sampled_rows": bool(np.array_equal(Zh.view(np.uint32),
+                                                                   Zr.view(np.uint32))),
+                      "rel_frobenius_err_vs_f64": oracle.rel_frobenius(Zh, Z64),
+                      "kernel_config": list(afmm.default_config("A", n))},
+           "split": {"ms": split_ms, "effective_2n3_per_s": 2.0 * n ** 3 / (split_ms * 1e-3),
+                     "mfma_frac_of_bf16_peak": 6.0 * n ** 3 / (split_ms * 1e-3) / 1e12
+                     / PEAK_BF16_TFLOPS,
+                     "rel_frobenius_err_vs_f64": oracle.rel_frobenius(Zsh, Z64),
+                     "speedup_over_strict": strict_ms / split_ms},
+           "err_sample": f"{len(sample)} rows"}
+    print(json.dumps(out), flush=True)
+
+
 def table1(args):
     """Section 2.3.1 / Table 1 grid: case A, d1 = 1/3, d2 = 1/2 for mu' <= 7 and 1/5, 2/5
     for 14 and 21.  The distribution of Y's non-zeros is not stated; both readings are run:
@@ -243,6 +298,8 @@ def main():
         sys.exit(2)
     if args.table1:
         return table1(args)
+    if args.c5:
+        return c5(args)
     import numpy as np
     import torch
 
