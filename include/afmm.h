@@ -69,7 +69,7 @@ typedef enum {
     AFMM_ERR_COUNT_OVERFLOW = 5, /* afmm_validate: the add count exceeds 2^64 - 1      */
     AFMM_ERR_NO_DEVICE = 6,      /* no usable gfx950 device                            */
     AFMM_ERR_HIP = 7,            /* a HIP call failed; see afmm_last_hip_error()       */
-    AFMM_ERR_UNSUPPORTED = 8,    /* valid request this build does not implement        */
+    AFMM_ERR_UNSUPPORTED = 8,    /* valid request the library does not implement       */
     AFMM_ERR_WORKSPACE = 9       /* workspace given but smaller than required          */
 } afmm_status;
 
@@ -165,7 +165,7 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            factor's columns; case A runs on the transposed problem),
  *            1 = base-uniform (case A only: each wave walks R rows of X with
  *            the base in a scalar register; lanes over Y's columns with a
- *            per-lane count; not compiled in this build),
+ *            per-lane count; not compiled into the library),
  *            2 = rep-uniform with base rows streamed straight into
  *            registers (no LDS panel); falls back to 0 when the base rows
  *            are not readable in 16-byte units (case B with n % 4 != 0),
