@@ -245,7 +245,16 @@ __device__ __forceinline__ void rep_uniform_tile(
 #pragma unroll
         for (int kk = 0; kk < KP; ++kk) {
             float* b = (kk & 1) ? bB : bA;
-            if (kk + 1 < KP) lds_row((kk & 1) ? bA : bB, kk + 1);
+            // row kk's reads are done once no more than row kk + 1's G reads are
+            // outstanding (LDS reads return in order): one wait per k, where the
+            // compiler would otherwise wait inside every repetition loop
+            static_assert(G <= 15, "lgkmcnt holds 4 bits");
+            if (kk + 1 < KP) {
+                lds_row((kk & 1) ? bA : bB, kk + 1);
+                __builtin_amdgcn_s_waitcnt(0xC07F | (G << 8));  // lgkmcnt(G)
+            } else {
+                __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint32_t word = __builtin_amdgcn_readfirstlane(cw[r].get(kk >> 2));
