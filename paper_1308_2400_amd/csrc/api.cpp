@@ -216,7 +216,7 @@ afmm_config lds_config(int64_t n) {
 // keeps n around 4096 in case B.
 afmm_config builtin_config(afmm_case c, int64_t n) {
     if (n > 5792 || (c == AFMM_CASE_A && n > 2896)) return afmm_config{3, 2, 16, 16, 2, 8};
-    if (n > 2896) return afmm_config{0, 4, 16, 16, 1, 16};
+    if (n > 2896) return afmm_config{0, 4, 16, 16, 2, 16};
     if (n > 1448) return afmm_config{3, 1, 16, 16, 1, 8};
     return lds_config(n);
 }

@@ -8,7 +8,8 @@ namespace afmm {
     X(4, 16, 8, 1, 8)       \
     X(4, 16, 8, 2, 8)       \
     X(6, 16, 4, 1, 8)       \
-    X(4, 16, 16, 1, 16)
+    X(4, 16, 16, 1, 16)     \
+    X(4, 16, 16, 2, 16)
 
 // With a == nullptr: is (R, C, W, U, KP) compiled here?  Otherwise launch it.
 bool rep_part_a(const StrictArgs* a, int R, int C, int W, int U, int KP, hipStream_t s,

@@ -67,7 +67,7 @@ def test_rect_strict_bitexact(dev, case, shape):
     assert np.array_equal(_bits(Z), _bits(Zr))
 
 
-CFGS = [(0, 4, 16, 16, 1, 16), (0, 2, 1, 4, 1, 16), (0, 4, 2, 4, 2, 16), (2, 8, 8, 4),
+CFGS = [(0, 4, 16, 16, 1, 16), (0, 4, 16, 16, 2, 16), (0, 2, 1, 4, 1, 16), (0, 4, 2, 4, 2, 16), (2, 8, 8, 4),
         (3, 2, 16, 16, 1, 8), (3, 2, 8, 16, 2, 16), (3, 1, 16, 16, 1, 8)]
 
 
