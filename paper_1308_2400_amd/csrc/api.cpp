@@ -210,12 +210,12 @@ afmm_config lds_config(int64_t n) {
 }
 
 // Built-in rule, used when no tuning table is loaded: what the autotuner picked
-// on MI355X.  The sparse-k variant wins wherever the counts leave many k
-// empty for a pair of rows (case A's real factor is the sparse one here, and
-// n = 2048 needs its 16-row tiles to fill the chip); the LDS-panel variant
-// keeps n around 4096 in case B.
+// on MI355X.  The sparse-k variant wins where the counts leave many k empty for
+// a pair of rows (case A above n = 5792) and at n = 2048, where its 16-row tiles
+// fill the chip; the LDS-panel variant with 16-column lanes elsewhere above 2896.
 afmm_config builtin_config(afmm_case c, int64_t n) {
-    if (n > 5792 || (c == AFMM_CASE_A && n > 2896)) return afmm_config{3, 2, 16, 16, 2, 8};
+    if (c == AFMM_CASE_A && n > 5792) return afmm_config{3, 2, 16, 16, 2, 8};
+    if (c == AFMM_CASE_A && n > 2896) return afmm_config{0, 4, 16, 8, 2, 8};
     if (n > 2896) return afmm_config{0, 4, 16, 16, 2, 16};
     if (n > 1448) return afmm_config{3, 1, 16, 16, 1, 8};
     return lds_config(n);
