@@ -87,7 +87,11 @@ def test_rectangular_argument_errors_on_host(afmm):
     assert fA(70000, 8, 6, X, 8, Y, 6, Z, 6, 0, None, 0, None) == 1
     # Z's range (m-1)*ldz + n elements overlaps X's (m-1)*ldx + k
     assert fA(3, 5, 2, X, 100, Y, 2, X + 4 * 150, 2, 0, None, 0, None) == 2
-    assert fA(3, 5, 2, X, 5, Y, 2, X + 4 * 15, 2, 0, None, 0, None) != 2
+    # adjacent ranges are no alias: the call gets past that check and stops at the
+    # invalid mode after it (every call here must fail on the host: the addresses
+    # are placeholders, and a valid call would launch kernels on them on a machine
+    # with a GPU)
+    assert fA(3, 5, 2, X, 5, Y, 2, X + 4 * 15, 2, 7, None, 0, None) == 1
     # counting: bad leading dimension
     assert afmm.afmm_count_adds_ex(1, 4, 8, 6, X, 7, Y, 6, Z, None, None, None, 0, None) == 1
 
@@ -116,6 +120,8 @@ def test_config_table(afmm):
     assert afmm.config_supported("A", (3, 2, 16, 16, 1, 8))  # sparse-k variant
     assert afmm.config_supported("B", (3, 4, 8, 16, 2, 16))
     assert not afmm.config_supported("B", (3, 2, 16, 16, 1, 16))  # 128 KB of LDS: not built
+    assert afmm.config_supported("A", (4, 4, 16, 8, 1, 16))  # compacted-base variant
+    assert not afmm.config_supported("A", (4, 4, 16, 8, 1, 8))  # 16-k count words only
     afmm.set_tuning([])
     builtin = afmm.default_config("B", 4096)
     afmm.set_tuning([("B", 1000, 5000, (0, 4, 4, 4))])
@@ -143,3 +149,22 @@ def test_binding_fails_loudly_without_library(tmp_path):
     (tmp_path / "pkg" / "__init__.py").write_text(src)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert r.returncode != 0 and "is not built" in r.stderr
+
+
+def test_workspace_per_config(afmm):
+    """The compacted-base form needs room for its lists: 8 bytes per lane column
+    (rounded up to the band) per k (rounded up to 16), plus the lengths."""
+    n = 1000
+    base = afmm.workspace_size("A", n, config=(0, 4, 16, 16, 1, 16))
+    acc = afmm.workspace_size("A", n, config=(4, 4, 16, 8, 1, 16))
+    lists = 8 * 1024 * 1008
+    assert base > 0 and acc >= base + lists
+    assert afmm.workspace_size("A", n, config=(4, 4, 4, 8, 1, 16)) >= base + 8 * 1024 * 1008
+    assert afmm.workspace_size("A", n, config=(0, 3, 3, 3)) == 0  # not compiled
+    afmm.set_tuning([])
+    try:
+        afmm.set_tuning([("A", 1, 1 << 30, (4, 4, 16, 8, 1, 16))])
+        assert afmm.workspace_size("A", n) == acc  # the picked configuration's needs
+    finally:
+        afmm.set_tuning([])
+        afmm.load_tuning()
