@@ -173,9 +173,21 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            loaded straight into LDS, and each wave visits only the k where
  *            one of its R rows has a non-zero count; falls back to 0 when
  *            the base rows are not readable in 16-byte units or the base
- *            matrix exceeds 2^31 bytes.
+ *            matrix exceeds 2^31 bytes,
+ *            4 = rep-uniform, compacted base, for a real factor with few
+ *            non-zeros: a pass lists the non-zero bases of every k in bands
+ *            of 64*C lane columns; a workgroup keeps a (W*R) x (64*C) block
+ *            of Z in LDS, and for each k its lanes take the listed bases
+ *            (64 at a time) while each wave walks its R rows with the count
+ *            uniform, reading, repeatedly adding to and writing back its Z
+ *            elements.  Lanes never idle on a zero base.  The lists take
+ *            8 * round_up(lane extent, 64*C) * round_up(k, 16) bytes of
+ *            workspace (afmm_workspace_size_config); falls back to 0 when one
+ *            band of them or the count bytes exceed 2^31 bytes.
  *   rows_per_wave R, cols_per_lane C, waves per workgroup W, unroll U (1
- *   or 2: the repetition loop does U additions per trip; 0 means 1),
+ *   or 2: the repetition loop does U additions per trip; 4, mapping 4
+ *   only: one, two and four additions under tests of the count's low bits,
+ *   then trips of eight; 0 means 1),
  *   k_panel (rows of the base staged per LDS panel, 4, 8 or 16; 0 means 16):
  *   one of the compiled combinations (afmm_config_supported tells which).
  *   Every configuration performs the same additions in the same order, so
@@ -196,6 +208,10 @@ int afmm_config_supported(afmm_case c, const afmm_config *cfg);
 /* The configuration the library picks for a strict product of this case and
  * size (tuning table, else built-in rule). */
 afmm_config afmm_default_config(afmm_case c, int64_t n);
+
+/* Workspace bytes of a strict n x n product run with `cfg` (0 when cfg is not
+ * compiled); afmm_workspace_size covers the configuration the library picks. */
+size_t afmm_workspace_size_config(afmm_case c, int64_t n, const afmm_config *cfg);
 
 /* Strict product with an explicit configuration (for the autotuner). */
 afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void *X, const void *Y,

@@ -66,6 +66,7 @@ _SIGS = {
     "afmm_validate": ([_ci, _i64, _vp, _vp, _ci, _vp], _ci),
     "afmm_config_supported": ([_ci, ctypes.POINTER(afmm_config)], _ci),
     "afmm_default_config": ([_ci, _i64], afmm_config),
+    "afmm_workspace_size_config": ([_ci, _i64, ctypes.POINTER(afmm_config)], _sz),
     "afmm_multiply_strict_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config), _vp,
                                      _sz, _vp], _ci),
     "afmm_set_tuning": ([_i32, _vp, _vp, _vp, _vp], _ci),
@@ -165,7 +166,11 @@ def _operands(case, X, Y):
     return c, n
 
 
-def workspace_size(case, n, mode="strict") -> int:
+def workspace_size(case, n, mode="strict", config=None) -> int:
+    """Workspace bytes of a square product; with `config`, of the strict product
+    run with that kernel configuration (0 if it is not compiled)."""
+    if config is not None:
+        return int(_lib.afmm_workspace_size_config(_case_id(case), n, ctypes.byref(_cfg(config))))
     return int(_lib.afmm_workspace_size(_case_id(case), n, _mode_id(mode)))
 
 
@@ -191,7 +196,7 @@ def multiply(case, X, Y, mode="strict", out=None, workspace=None, config=None):
     if workspace is None:
         need = workspace_size(c, n, md) if square else workspace_size_ex(c, m, k, n, md)
         if config is not None and square:
-            need = max(need, workspace_size(c, n, MODE_STRICT))
+            need = max(need, workspace_size(c, n, MODE_STRICT, config=config))
         workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
     ws, wsb = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     if config is not None:

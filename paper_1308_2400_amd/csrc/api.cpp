@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "strict_acc.hpp"
 
 static int& g_last_hip_error_slot() {
     static thread_local int e = 0;
@@ -106,14 +107,15 @@ struct Carve {
 struct StrictLayout {
     int rows_pad;
     int64_t ldp, ldq;
-    size_t p8, xt, esc, total;
+    size_t p8, xt, esc, acc, total;
 };
 
 // Strict path: count bytes P8 [rows_pad x ldp] of the integer factor, rows
 // being the count-uniform side (case B: i < m; case A: j < n) and columns k;
 // case A also keeps its real factor transposed, Xt [round_up(k) x ldq], ldq
-// covering i < m.
-StrictLayout strict_layout(afmm_case c, const Shape& p) {
+// covering i < m.  The compacted-base form (mapping 4) adds its lists of
+// non-zero bases.
+StrictLayout strict_layout(afmm_case c, const Shape& p, const afmm_config& cfg) {
     StrictLayout L;
     L.rows_pad = (int)round_up(c == AFMM_CASE_B ? p.m : p.n, kRowPad);
     L.ldp = round_up(p.k, kKPad);
@@ -122,6 +124,9 @@ StrictLayout strict_layout(afmm_case c, const Shape& p) {
     L.p8 = cv.take((size_t)L.rows_pad * L.ldp);
     L.xt = c == AFMM_CASE_A ? cv.take((size_t)round_up(p.k, kKPad) * L.ldq * 4) : 0;
     L.esc = cv.take(4);
+    L.acc = cfg.mapping == 4 ? cv.take(acc_lists_bytes((int)(c == AFMM_CASE_B ? p.n : p.m),
+                                                       (int)p.k, cfg.cols_per_lane))
+                             : 0;
     L.total = cv.off;
     return L;
 }
@@ -192,6 +197,7 @@ bool config_ok(afmm_case c, const afmm_config& g) {
     if (g.mapping == 3)
         return rep_sparse_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (kp != 16) return false;
+    if (g.mapping == 4) return rep_acc_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u);
     if (u != 1) return false;
     if (g.mapping == 1)
         return c == AFMM_CASE_A && base_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
@@ -210,9 +216,10 @@ afmm_config lds_config(int64_t n) {
 }
 
 // Built-in rule, used when no tuning table is loaded: what the autotuner picked
-// on MI355X.  The sparse-k variant wins where the counts leave many k empty for
-// a pair of rows (case A above n = 5792) and at n = 2048, where its 16-row tiles
-// fill the chip; the LDS-panel variant with 16-column lanes elsewhere above 2896.
+// on MI355X.  The sparse-k variant at n = 2048, where its 16-row tiles fill the
+// chip, and for case A above 5792 (even with the LDS-panel variant there); the
+// LDS-panel variant with 16-column lanes elsewhere above 2896.  The compacted-base
+// variant is never picked by size: it wins only on a sparse real factor.
 afmm_config builtin_config(afmm_case c, int64_t n) {
     if (c == AFMM_CASE_A && n > 5792) return afmm_config{3, 2, 16, 16, 2, 8};
     if (c == AFMM_CASE_A && n > 2896) return afmm_config{0, 4, 16, 8, 2, 8};
@@ -223,7 +230,7 @@ afmm_config builtin_config(afmm_case c, int64_t n) {
 
 afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
                        const afmm_config& cfg, void* ws, size_t ws_bytes, hipStream_t s) {
-    const StrictLayout L = strict_layout(c, p);
+    const StrictLayout L = strict_layout(c, p, cfg);
     Scratch sc;
     const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
     if (st != AFMM_OK) return st;
@@ -269,15 +276,21 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
         a.trans_out = true;
         a.q_padded = true;
     }
-    if (cfg.mapping == 2 && rep_direct_usable(a)) {
+    if (cfg.mapping == 4 && rep_acc_usable(a, cfg.cols_per_lane)) {
+        const AccLists lists = acc_lists_at(sc.at(L.acc), a.n_c, a.n_k, cfg.cols_per_lane);
+        AFMM_HIP(launch_compact_base(a.Q, a.ldq, a.n_k, a.n_c, cfg.cols_per_lane, lists, s));
+        AFMM_HIP(launch_rep_acc(a, lists, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves,
+                                cfg.unroll == 0 ? 1 : cfg.unroll, s));
+    } else if (cfg.mapping == 2 && rep_direct_usable(a)) {
         AFMM_HIP(launch_rep_direct(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
     } else if (cfg.mapping == 3 && rep_sparse_usable(a)) {
         AFMM_HIP(launch_rep_sparse(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves,
                                    cfg.unroll == 0 ? 1 : cfg.unroll,
                                    cfg.k_panel == 0 ? 16 : cfg.k_panel, s));
-    } else if (cfg.mapping == 2 || cfg.mapping == 3 || cfg.mapping == 0) {
-        // the direct and sparse-k variants need float4-readable base rows (the
-        // sparse-k one also 31-bit offsets); the LDS-panel variant takes the rest
+    } else if (cfg.mapping == 2 || cfg.mapping == 3 || cfg.mapping == 4 || cfg.mapping == 0) {
+        // the direct and sparse-k variants need float4-readable base rows, the
+        // sparse-k and compacted-base ones 31-bit offsets; the LDS-panel variant
+        // takes the rest
         const afmm_config d = cfg.mapping == 0 ? cfg : lds_config(shape_size(p));
         AFMM_HIP(launch_rep_uniform(a, d.rows_per_wave, d.cols_per_lane, d.waves,
                                     d.unroll == 0 ? 1 : d.unroll,
@@ -317,7 +330,8 @@ afmm_status split_run(afmm_case c, const Shape& p, const void* X, const void* Y,
 
 size_t workspace_for(afmm_case c, const Shape& p, afmm_mode mode) {
     if (mode == AFMM_MODE_SPLIT_BF16X3) return split_layout(c, p).total;
-    return std::max(strict_layout(c, p).total, count_ws(p));
+    const afmm_config cfg = afmm_default_config(c, shape_size(p));
+    return std::max(strict_layout(c, p, cfg).total, count_ws(p));
 }
 
 afmm_status multiply(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
@@ -358,6 +372,13 @@ extern "C" {
 size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode) {
     if (n < 1 || n > AFMM_MAX_N || (c != AFMM_CASE_A && c != AFMM_CASE_B)) return 0;
     return workspace_for(c, square(n), mode);
+}
+
+size_t afmm_workspace_size_config(afmm_case c, int64_t n, const afmm_config* cfg) {
+    if (n < 1 || n > AFMM_MAX_N || (c != AFMM_CASE_A && c != AFMM_CASE_B) || !cfg ||
+        !config_ok(c, *cfg))
+        return 0;
+    return std::max(strict_layout(c, square(n), *cfg).total, count_ws(square(n)));
 }
 
 size_t afmm_workspace_size_ex(afmm_case c, int64_t m, int64_t k, int64_t n, afmm_mode mode) {

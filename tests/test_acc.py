@@ -1,0 +1,106 @@
+"""GPU parity of the compacted-base strict form (mapping 4) against the CPU oracle.
+
+The form lists each k's non-zero bases per band of lane columns and keeps the Z
+block in LDS; it must give the oracle's bits exactly like every other form.  Cases
+cover ragged sizes, real-factor densities from 2 % (C5-like) to 100 % (segments
+longer than 64 entries, walked in several chunks), -0.0 bases (skipped like +0.0),
+counts of 255 and more (escape path), an all-zero real factor, and sampled rows of
+the n=16384 case-A workload.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ACC = [(4, 4, 16, 8, 1, 16), (4, 4, 16, 8, 2, 16), (4, 4, 16, 8, 4, 16), (4, 2, 16, 16, 1, 16),
+       (4, 2, 16, 16, 2, 16), (4, 2, 16, 16, 4, 16), (4, 4, 8, 16, 1, 16), (4, 8, 8, 8, 1, 16),
+       (4, 4, 4, 8, 1, 16)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    import paper_1308_2400_amd  # noqa: F401  (fails loudly when libafmm.so is missing)
+    return torch.device("cuda:0")
+
+
+def _afmm():
+    import paper_1308_2400_amd
+    return paper_1308_2400_amd
+
+
+def _to(dev, a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def _inputs(case, n, seed, d_real, int_hi=6, d_int=0.7):
+    r = np.random.default_rng(seed)
+    real = r.uniform(-1, 1, (n, n)).astype(np.float32)
+    real[r.random((n, n)) > d_real] = 0
+    real[(real == 0) & (r.random((n, n)) < 0.5)] = -0.0  # a zero base of either sign
+    ints = r.integers(0, int_hi + 1, (n, n)).astype(np.int32)
+    ints[r.random((n, n)) > d_int] = 0
+    return (real, ints) if case == "A" else (ints, real)
+
+
+def _check_all(dev, case, X, Y, configs=ACC):
+    afmm = _afmm()
+    Zref, _ = oracle.strict_f32(case, X, Y)
+    Xd, Yd = _to(dev, X), _to(dev, Y)
+    for cfg in configs:
+        assert afmm.config_supported(case, cfg), cfg
+        Z = afmm.multiply(case, Xd, Yd, "strict", config=cfg).cpu().numpy()
+        same = np.array_equal(_bits(Z), _bits(Zref))
+        if not same:
+            d = np.argwhere(_bits(Z) != _bits(Zref))
+            pytest.fail(f"{cfg}: {len(d)} elements differ, first {tuple(d[0])}")
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("n", [1, 7, 130, 515, 1100])
+def test_acc_sizes_and_densities(dev, case, n):
+    for d_real in (0.02, 0.3, 1.0):
+        X, Y = _inputs(case, n, 900 + n + int(100 * d_real), d_real)
+        _check_all(dev, case, X, Y)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_acc_escape_counts(dev, case):
+    """Counts of 255 and more re-read from the int32 factor."""
+    n = 200
+    X, Y = _inputs(case, n, 31, 0.1)
+    ints = Y if case == "A" else X
+    r = np.random.default_rng(5)
+    ints[:] = r.integers(200, 400, ints.shape)
+    ints[r.random(ints.shape) < 0.6] = 0
+    _check_all(dev, case, X, Y)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_acc_zero_real_factor(dev, case):
+    n = 300
+    X, Y = _inputs(case, n, 8, 0.0)
+    afmm = _afmm()
+    for cfg in ACC[:2]:
+        Z = afmm.multiply(case, _to(dev, X), _to(dev, Y), "strict", config=cfg).cpu().numpy()
+        assert (_bits(Z) == 0).all()  # +0.0 everywhere
+
+
+def test_acc_caseA_n16384_sampled(dev):
+    """The n=16384 case-A workload (real factor 5 % dense) on sampled rows."""
+    w = gen.caseA_n16384()
+    X, Y = w.X(), w.Y()
+    rows = [17, 16383]
+    afmm = _afmm()
+    Z = afmm.multiply("A", _to(dev, X), _to(dev, Y), "strict", config=ACC[0]).cpu().numpy()
+    Zref, _ = oracle.strict_f32("A", X[rows], Y, rows=rows, x_rows_only=True)
+    assert np.array_equal(_bits(Z[rows]), _bits(Zref))

@@ -78,7 +78,9 @@ CONFIGS = [(0, 8, 8, 8), (0, 8, 8, 8, 2), (0, 4, 8, 8), (0, 8, 4, 8), (0, 8, 4, 
            (0, 6, 16, 4, 1, 8), (0, 8, 8, 8, 2, 8), (0, 4, 16, 16, 1, 16), (0, 4, 16, 16, 2, 16),
            (2, 8, 8, 4), (2, 4, 8, 8), (2, 16, 4, 4),
            (3, 2, 16, 16, 1, 8), (3, 2, 16, 16, 2, 8), (3, 4, 8, 16, 1, 16), (3, 4, 8, 16, 2, 16),
-           (3, 2, 8, 16, 2, 16), (3, 2, 16, 8, 1, 4), (3, 2, 16, 8, 2, 4), (3, 1, 16, 16, 1, 8)]
+           (3, 2, 8, 16, 2, 16), (3, 2, 16, 8, 1, 4), (3, 2, 16, 8, 2, 4), (3, 1, 16, 16, 1, 8),
+           (4, 4, 16, 8, 1, 16), (4, 4, 16, 8, 2, 16), (4, 2, 16, 16, 1, 16), (4, 4, 8, 16, 1, 16),
+           (4, 8, 8, 8, 1, 16), (4, 4, 4, 8, 1, 16)]
 SPARSE = [c for c in CONFIGS if c[0] == 3]
 
 
@@ -128,7 +130,8 @@ def test_counts_with_top_bit_set(dev, case):
     ints = X if case == "B" else Y
     ints[:] = r.integers(128, 255, ints.shape)
     ints[r.random(ints.shape) < 0.5] = 0
-    for cfg in [(0, 4, 16, 16, 1, 16), (0, 4, 16, 16, 2, 16), (2, 8, 8, 4)] + SPARSE:
+    for cfg in [(0, 4, 16, 16, 1, 16), (0, 4, 16, 16, 2, 16), (2, 8, 8, 4), (4, 4, 16, 8, 1, 16),
+                (4, 4, 4, 8, 1, 16)] + SPARSE:
         _check_strict(dev, case, X, Y, config=cfg)
 
 
