@@ -195,7 +195,7 @@ def empirical_fit(rows):
 
 # compacted-base configuration for a real factor with few non-zeros (autotuner's
 # pick on the n=16384 case-A distribution at n = 2048..8192)
-SPARSE_REAL_CONFIG = (4, 2, 16, 16, 2, 16)
+SPARSE_REAL_CONFIG = (4, 2, 32, 8, 2, 8)
 
 
 def c5(args):

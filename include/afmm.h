@@ -178,9 +178,11 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            non-zeros: a pass lists the non-zero bases of every k in bands
  *            of 64*C lane columns; a workgroup keeps a (W*R) x (64*C) block
  *            of Z in LDS, and for each k its lanes take the listed bases
- *            (64 at a time) while each wave walks its R rows with the count
- *            uniform, reading, repeatedly adding to and writing back its Z
- *            elements.  Lanes never idle on a zero base.  The lists take
+ *            (max(1, C/16) per lane, 64 lanes at a time) while each wave walks
+ *            its R rows with the count uniform, reading, repeatedly adding to
+ *            and writing back its Z elements.  Lanes never idle on a zero
+ *            base; k_panel (8 or 16) is the number of k whose lists and
+ *            counts are fetched ahead together.  The lists take
  *            8 * round_up(lane extent, 64*C) * round_up(k, 16) bytes of
  *            workspace (afmm_workspace_size_config); falls back to 0 when one
  *            band of them or the count bytes exceed 2^31 bytes.

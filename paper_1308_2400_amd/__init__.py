@@ -256,7 +256,8 @@ def validate(case, X, Y, mode="strict") -> int:
 
 
 def default_config(case, n):
-    """(mapping, R, C, W, unroll) the library uses for a strict product of this size."""
+    """(mapping, R, C, W, unroll, k_panel) the library uses for a strict product of this
+    size (tuning table, else the built-in rule)."""
     return _lib.afmm_default_config(_case_id(case), n).as_tuple()
 
 
@@ -269,7 +270,8 @@ def config_supported(case, cfg) -> bool:
 
 
 def set_tuning(entries):
-    """entries: iterable of (case, n_lo, n_hi, (mapping, R, C, W[, unroll]))."""
+    """entries: iterable of (case, n_lo, n_hi, (mapping, R, C, W[, unroll[, k_panel]]));
+    replaces the table (an entry naming an uncompiled configuration is rejected)."""
     entries = list(entries)
     k = len(entries)
     cases = (ctypes.c_int32 * max(k, 1))(*[_case_id(e[0]) for e in entries])

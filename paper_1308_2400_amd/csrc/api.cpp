@@ -196,8 +196,9 @@ bool config_ok(afmm_case c, const afmm_config& g) {
         return rep_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (g.mapping == 3)
         return rep_sparse_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
+    if (g.mapping == 4)
+        return rep_acc_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (kp != 16) return false;
-    if (g.mapping == 4) return rep_acc_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u);
     if (u != 1) return false;
     if (g.mapping == 1)
         return c == AFMM_CASE_A && base_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
@@ -280,7 +281,8 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
         const AccLists lists = acc_lists_at(sc.at(L.acc), a.n_c, a.n_k, cfg.cols_per_lane);
         AFMM_HIP(launch_compact_base(a.Q, a.ldq, a.n_k, a.n_c, cfg.cols_per_lane, lists, s));
         AFMM_HIP(launch_rep_acc(a, lists, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves,
-                                cfg.unroll == 0 ? 1 : cfg.unroll, s));
+                                cfg.unroll == 0 ? 1 : cfg.unroll,
+                                cfg.k_panel == 0 ? 16 : cfg.k_panel, s));
     } else if (cfg.mapping == 2 && rep_direct_usable(a)) {
         AFMM_HIP(launch_rep_direct(a, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves, s));
     } else if (cfg.mapping == 3 && rep_sparse_usable(a)) {

@@ -15,7 +15,7 @@
 
 namespace afmm {
 
-constexpr int kAccKP = 16;  // k per panel: one 16-byte count word per row
+constexpr int kAccKP = 16;  // k padding of the segment table (covers panels of 8 and 16 k)
 constexpr int kAccWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), other counters at their maxima
 
 size_t acc_lists_bytes(int n_c, int n_k, int C) {
@@ -78,64 +78,80 @@ hipError_t launch_compact_base(const float* Q, int64_t ldq, int n_k, int n_c, in
     return hipGetLastError();
 }
 
-template <int R, int C, int W>
+template <int R, int C, int W, int KP>
 struct AccTile {
-    static constexpr int CT = kWave * C;   // columns per block (one band)
-    static constexpr int TM = W * R;       // rows per block
-    static constexpr int STRIDE = CT + 1;  // LDS row pitch in floats
+    static constexpr int CT = kWave * C;        // columns per block (one band)
+    static constexpr int E = C >= 16 ? C / 16 : 1;  // entries per lane per k
+    static constexpr int TM = W * R;            // rows per block
+    // LDS row: the band's CT columns, then one sink column per lane (a lane
+    // without an entry adds +0.0 there), then one float that keeps rows on
+    // different banks
+    static constexpr int STRIDE = CT + kWave + 1;
     static constexpr int LDS_FLOATS = TM * STRIDE;
     static_assert(TM <= kRowPad, "row padding must cover a tile");
-    static_assert(LDS_FLOATS % 4 == 0, "the tile is cleared in float4 units");
+    static_assert(TM % 4 == 0, "the tile is cleared in float4 units");
     static_assert(LDS_FLOATS * 4 <= 160 * 1024, "the Z tile must fit in LDS");
+    static_assert(KP == 8 || KP == 16, "count words of 8 or 16 k");
+    static_assert(kKPad % KP == 0, "KP must divide the k padding");
 };
 
-// One chunk of up to 64 entries of the segment of k0 + kk: lanes below `act_`
-// hold an entry {base bits, column}.  Each of the wave's rows with a non-zero
-// count reads its Z element from LDS, adds the base `rep` times and writes it
-// back; the reads of all rows go out before the first addition.
-#define AFMM_ACC_CHUNK(ev_, act_)                                                              \
-    if (lane < (act_)) {                                                                       \
-        const int cl_ = (int)(ev_)[1];                                                         \
-        const float b_ = __uint_as_float((ev_)[0]);                                            \
-        float z_[R];                                                                           \
-        _Pragma("unroll") for (int r = 0; r < R; ++r) if (rep_[r] != 0) z_[r] =                \
-            arow[r * T::STRIDE + cl_];                                                         \
+// One chunk of up to 64*E entries of the segment of k0 + kk, slot q of lane l
+// holding entry ch_ + 64 q + l: a slot past the segment's end turns into a +0.0
+// base on the lane's sink column, so every lane runs every slot.  Each of the
+// wave's rows with a non-zero count reads its E Z elements from LDS, adds each
+// slot's base `rep` times (the E chains side by side) and writes them back; the
+// reads of all rows go out before the first addition.
+#define AFMM_ACC_CHUNK(ev_, ch_)                                                               \
+    {                                                                                          \
+        int col_[T::E];                                                                        \
+        float b_[T::E];                                                                        \
+        _Pragma("unroll") for (int q = 0; q < T::E; ++q) {                                     \
+            const bool ok_ = (ch_) + q * kWave + lane < len_;                                  \
+            col_[q] = ok_ ? (int)(ev_)[q][1] : T::CT + lane;                                   \
+            b_[q] = ok_ ? __uint_as_float((ev_)[q][0]) : 0.0f;                                 \
+        }                                                                                      \
+        float z_[R][T::E];                                                                     \
+        _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
+            if (rep_[r] == 0) continue;                                                        \
+            _Pragma("unroll") for (int q = 0; q < T::E; ++q) z_[r][q] =                        \
+                arow[r * T::STRIDE + col_[q]];                                                 \
+        }                                                                                      \
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);                                                \
         _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
             uint32_t n_ = rep_[r];                                                             \
             if (n_ == 0) continue;                                                             \
-            float zz_ = z_[r];                                                                 \
+            float zz_[T::E];                                                                   \
+            _Pragma("unroll") for (int q = 0; q < T::E; ++q) zz_[q] = z_[r][q];                \
             if (U == 4) {                                                                      \
                 /* bits of the count: 1, 2 and 4 additions under scalar bit */                 \
                 /* tests, then runs of 8 */                                                    \
-                if (n_ & 1u) zz_ = zz_ + b_;                                                   \
-                if (n_ & 2u) {                                                                 \
-                    zz_ = zz_ + b_;                                                            \
-                    zz_ = zz_ + b_;                                                            \
-                }                                                                              \
-                if (n_ & 4u) {                                                                 \
-                    _Pragma("unroll") for (int q_ = 0; q_ < 4; ++q_) zz_ = zz_ + b_;           \
-                }                                                                              \
-                for (n_ >>= 3; n_ != 0; --n_) {                                                \
-                    _Pragma("unroll") for (int q_ = 0; q_ < 8; ++q_) zz_ = zz_ + b_;           \
-                }                                                                              \
+                if (n_ & 1u) AFMM_ACC_ADD(1);                                                  \
+                if (n_ & 2u) AFMM_ACC_ADD(2);                                                  \
+                if (n_ & 4u) AFMM_ACC_ADD(4);                                                  \
+                for (n_ >>= 3; n_ != 0; --n_) AFMM_ACC_ADD(8);                                 \
             } else if (U == 2) {                                                               \
-                if (n_ & 1u) zz_ = zz_ + b_;                                                   \
-                for (n_ >>= 1; n_ != 0; --n_) {                                                \
-                    zz_ = zz_ + b_;                                                            \
-                    zz_ = zz_ + b_;                                                            \
-                }                                                                              \
+                if (n_ & 1u) AFMM_ACC_ADD(1);                                                  \
+                for (n_ >>= 1; n_ != 0; --n_) AFMM_ACC_ADD(2);                                 \
             } else {                                                                           \
                 do {                                                                           \
-                    zz_ = zz_ + b_;                                                            \
+                    AFMM_ACC_ADD(1);                                                           \
                 } while (--n_ != 0);                                                           \
             }                                                                                  \
-            arow[r * T::STRIDE + cl_] = zz_;                                                   \
+            _Pragma("unroll") for (int q = 0; q < T::E; ++q) arow[r * T::STRIDE + col_[q]] =   \
+                zz_[q];                                                                        \
         }                                                                                      \
     }
 
-// The additions of k0 + kk for the wave's R rows: the prefetched first 64
-// entries, then (segments longer than 64) the rest, 64 at a time.
+// `times` more repetitions of every slot's base (slots interleaved, each
+// slot's own additions in order)
+#define AFMM_ACC_ADD(times)                                                                    \
+    {                                                                                          \
+        _Pragma("unroll") for (int t_ = 0; t_ < (times); ++t_)                                 \
+            _Pragma("unroll") for (int q = 0; q < T::E; ++q) zz_[q] = zz_[q] + b_[q];          \
+    }
+
+// The additions of k0 + kk for the wave's R rows: the prefetched first 64*E
+// entries, then (longer segments) the rest, 64*E at a time.
 #define AFMM_ACC_K(kk)                                                                         \
     do {                                                                                       \
         const int len_ = Lc[kk];                                                               \
@@ -155,15 +171,18 @@ struct AccTile {
             any_ |= v_;                                                                        \
         }                                                                                      \
         if (any_ == 0) break;                                                                  \
-        AFMM_ACC_CHUNK(ec[kk], len_)                                                           \
-        for (int ch_ = kWave; ch_ < len_; ch_ += kWave) {                                      \
-            const u32x2_t e2_ = __builtin_amdgcn_raw_buffer_load_b64(                          \
-                ers, (uint32_t)(((k0 + (kk)) * T::CT + ch_ + lane) * 8), 0, 0);                \
-            AFMM_ACC_CHUNK(e2_, len_ - ch_)                                                    \
+        AFMM_ACC_CHUNK(ec[kk], 0)                                                              \
+        for (int ch2_ = kWave * T::E; ch2_ < len_; ch2_ += kWave * T::E) {                     \
+            u32x2_t e2_[T::E];                                                                 \
+            _Pragma("unroll") for (int q = 0; q < T::E; ++q) e2_[q] =                          \
+                __builtin_amdgcn_raw_buffer_load_b64(                                          \
+                    ers, (uint32_t)(((k0 + (kk)) * T::CT + ch2_ + q * kWave + lane) * 8), 0,   \
+                    0); /* ch2_ + q * 64 + lane < CT */                                        \
+            AFMM_ACC_CHUNK(e2_, ch2_)                                                          \
         }                                                                                      \
     } while (0)
 
-template <int R, int C, int W, int U, bool TRANS_OUT, bool ESC>
+template <int R, int C, int W, int U, int KP, bool TRANS_OUT, bool ESC>
 __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
                                              const uint8_t* __restrict__ P8, int64_t ldp,
                                              const int32_t* __restrict__ P32, int64_t p32_sr,
@@ -171,7 +190,7 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
                                              const int32_t* __restrict__ lens, int64_t n_k_pad,
                                              float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
                                              int r0, int band, float* lds) {
-    using T = AccTile<R, C, W>;
+    using T = AccTile<R, C, W, KP>;
     constexpr int NT = W * kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -179,7 +198,7 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
     const int c0 = band * T::CT;
     float* arow = lds + wave * R * T::STRIDE;
 
-    // Z starts at +0.0
+    // Z starts at +0.0 (the sink columns too: they only ever receive +0.0)
     float4* l4 = reinterpret_cast<float4*>(lds);
     for (int i = threadIdx.x; i < T::LDS_FLOATS / 4; i += NT) l4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
@@ -198,62 +217,69 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
     const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(P8), (short)0, (int)((int64_t)rows_bound * ldp), 0x00020000);
 
-    const int n_panels = (n_k + kAccKP - 1) / kAccKP;
-    int32_t Lc[kAccKP];
-    u32x2_t ec[kAccKP];
-    SparseCounts<16> cw[R];
+    const int n_panels = (n_k + KP - 1) / KP;
+    int32_t Lc[KP];
+    u32x2_t ec[KP][T::E];
+    SparseCounts<KP> cw[R];
     {
-        u32x4_t lv[kAccKP / 4];
-        CountFetch<16> cf[R];
+        u32x4_t lv[KP / 4];
+        CountFetch<KP> cf[R];
 #pragma unroll
-        for (int q = 0; q < kAccKP / 4; ++q)
+        for (int q = 0; q < KP / 4; ++q)
             lv[q] = __builtin_amdgcn_raw_buffer_load_b128(lrs, (uint32_t)(q * 16), 0, 0);
 #pragma unroll
-        for (int kk = 0; kk < kAccKP; ++kk)
-            ec[kk] = __builtin_amdgcn_raw_buffer_load_b64(
-                ers, (uint32_t)((kk * T::CT + lane) * 8), 0, 0);
+        for (int kk = 0; kk < KP; ++kk)
+#pragma unroll
+            for (int q = 0; q < T::E; ++q)
+                ec[kk][q] = __builtin_amdgcn_raw_buffer_load_b64(
+                    ers, (uint32_t)((kk * T::CT + q * kWave + lane) * 8), 0, 0);
 #pragma unroll
         for (int r = 0; r < R; ++r) cf[r].fetch(crs, (uint32_t)((rw0 + r) * ldp));
 #pragma unroll
-        for (int kk = 0; kk < kAccKP; ++kk) Lc[kk] = (int32_t)uniform_u32(lv[kk / 4][kk % 4]);
+        for (int kk = 0; kk < KP; ++kk) Lc[kk] = (int32_t)uniform_u32(lv[kk / 4][kk % 4]);
 #pragma unroll
         for (int r = 0; r < R; ++r) cf[r].to(cw[r]);
         // both ways into the loop arrive with nothing pending (see the end of
         // the loop body): an empty statement that reads the entries keeps
         // their loads above it and makes the compiler wait for them here
 #pragma unroll
-        for (int kk = 0; kk < kAccKP; ++kk) asm volatile("" ::"v"(ec[kk]));
+        for (int kk = 0; kk < KP; ++kk)
+#pragma unroll
+            for (int q = 0; q < T::E; ++q) asm volatile("" ::"v"(ec[kk][q]));
     }
 
     for (int p = 0; p < n_panels; ++p) {
-        const int k0 = p * kAccKP;
+        const int k0 = p * KP;
         const bool more = p + 1 < n_panels;
-        u32x4_t lv[kAccKP / 4];
-        u32x2_t en[kAccKP];
-        CountFetch<16> cf[R];
+        u32x4_t lv[KP / 4];
+        u32x2_t en[KP][T::E];
+        CountFetch<KP> cf[R];
         if (more) {
-            const int k1 = k0 + kAccKP;
+            const int k1 = k0 + KP;
 #pragma unroll
-            for (int q = 0; q < kAccKP / 4; ++q)
+            for (int q = 0; q < KP / 4; ++q)
                 lv[q] = __builtin_amdgcn_raw_buffer_load_b128(lrs, (uint32_t)((k1 + 4 * q) * 4), 0, 0);
 #pragma unroll
-            for (int kk = 0; kk < kAccKP; ++kk)
-                en[kk] = __builtin_amdgcn_raw_buffer_load_b64(
-                    ers, (uint32_t)(((k1 + kk) * T::CT + lane) * 8), 0, 0);
+            for (int kk = 0; kk < KP; ++kk)
+#pragma unroll
+                for (int q = 0; q < T::E; ++q)
+                    en[kk][q] = __builtin_amdgcn_raw_buffer_load_b64(
+                        ers, (uint32_t)(((k1 + kk) * T::CT + q * kWave + lane) * 8), 0, 0);
 #pragma unroll
             for (int r = 0; r < R; ++r) cf[r].fetch(crs, (uint32_t)((rw0 + r) * ldp + k1));
         }
 #pragma unroll
-        for (int kk = 0; kk < kAccKP; ++kk) AFMM_ACC_K(kk);
+        for (int kk = 0; kk < KP; ++kk) AFMM_ACC_K(kk);
         // the next panel's loads have had this whole panel to land; waiting for
         // them here leaves nothing pending at the top of the loop, so the uses
         // of the entries there need no wait of their own
         __builtin_amdgcn_s_waitcnt(kAccWaitVm0);
         if (more) {
 #pragma unroll
-            for (int kk = 0; kk < kAccKP; ++kk) {
+            for (int kk = 0; kk < KP; ++kk) {
                 Lc[kk] = (int32_t)uniform_u32(lv[kk / 4][kk % 4]);
-                ec[kk] = en[kk];
+#pragma unroll
+                for (int q = 0; q < T::E; ++q) ec[kk][q] = en[kk][q];
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) cf[r].to(cw[r]);
@@ -277,57 +303,63 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
     }
 }
 #undef AFMM_ACC_K
+#undef AFMM_ACC_ADD
 #undef AFMM_ACC_CHUNK
 
-template <int R, int C, int W, int U, bool TRANS_OUT>
+template <int R, int C, int W, int U, int KP, bool TRANS_OUT>
 __global__ __launch_bounds__(W * kWave) void rep_acc_kernel(
     int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
     const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk, const uint2* __restrict__ ent,
     const int32_t* __restrict__ lens, int64_t n_k_pad, float* __restrict__ Z, int64_t z_sr,
     int64_t z_sc, const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles) {
-    using T = AccTile<R, C, W>;
+    using T = AccTile<R, C, W, KP>;
     __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     if (*esc)
-        rep_acc_tile<R, C, W, U, TRANS_OUT, true>(n_r, n_c, n_k, P8, ldp, P32, p32_sr, p32_sk, ent,
-                                                  lens, n_k_pad, Z, z_sr, z_sc, rb * T::TM, band,
-                                                  lds);
+        rep_acc_tile<R, C, W, U, KP, TRANS_OUT, true>(n_r, n_c, n_k, P8, ldp, P32, p32_sr, p32_sk,
+                                                      ent, lens, n_k_pad, Z, z_sr, z_sc,
+                                                      rb * T::TM, band, lds);
     else
-        rep_acc_tile<R, C, W, U, TRANS_OUT, false>(n_r, n_c, n_k, P8, ldp, P32, p32_sr, p32_sk,
-                                                   ent, lens, n_k_pad, Z, z_sr, z_sc, rb * T::TM,
-                                                   band, lds);
+        rep_acc_tile<R, C, W, U, KP, TRANS_OUT, false>(n_r, n_c, n_k, P8, ldp, P32, p32_sr,
+                                                       p32_sk, ent, lens, n_k_pad, Z, z_sr, z_sc,
+                                                       rb * T::TM, band, lds);
 }
 
-template <int R, int C, int W, int U>
+template <int R, int C, int W, int U, int KP>
 hipError_t launch_acc(const StrictArgs& a, const AccLists& L, hipStream_t s) {
-    using T = AccTile<R, C, W>;
+    using T = AccTile<R, C, W, KP>;
     if (!rep_acc_usable(a, C)) return hipErrorInvalidValue;
     const int n_row_blocks = (a.n_r + T::TM - 1) / T::TM;
     const int n_tiles = n_row_blocks * ((a.n_c + T::CT - 1) / T::CT);
     dim3 grid(n_tiles), block(W * kWave);
     if (a.trans_out)
-        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, true>), grid, block, 0, s, a.n_r, a.n_c,
-                           a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
+        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, KP, true>), grid, block, 0, s, a.n_r,
+                           a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
                            L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles);
     else
-        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, false>), grid, block, 0, s, a.n_r, a.n_c,
-                           a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
+        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, KP, false>), grid, block, 0, s, a.n_r,
+                           a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
                            L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles);
     return hipGetLastError();
 }
 
-// (R, C, W, U): TM = W*R rows x CT = 64*C columns of Z in LDS per block
+// (R, C, W, U, KP): TM = W*R rows x CT = 64*C columns of Z in LDS per block;
+// each lane takes max(1, C/16) entries of a k's segment
 #define AFMM_ACC_CONFIGS(X) \
-    X(4, 16, 8, 1)          \
-    X(4, 16, 8, 2)          \
-    X(4, 16, 8, 4)          \
-    X(2, 16, 16, 1)         \
-    X(2, 16, 16, 2)         \
-    X(2, 16, 16, 4)         \
-    X(4, 8, 16, 1)          \
-    X(8, 8, 8, 1)           \
-    X(4, 4, 8, 1)
+    X(4, 16, 8, 1, 16)      \
+    X(4, 16, 8, 2, 16)      \
+    X(4, 16, 8, 4, 16)      \
+    X(2, 16, 16, 1, 16)     \
+    X(2, 16, 16, 2, 16)     \
+    X(2, 16, 16, 4, 16)     \
+    X(4, 8, 16, 1, 16)      \
+    X(8, 8, 8, 1, 16)       \
+    X(4, 4, 8, 1, 16)       \
+    X(2, 32, 8, 2, 8)       \
+    X(1, 32, 16, 2, 8)      \
+    X(1, 64, 8, 2, 8)       \
+    X(1, 64, 8, 1, 8)
 
 bool rep_acc_usable(const StrictArgs& a, int C) {
     // buffer-resource byte offsets of one band's segments and of the count
@@ -337,18 +369,18 @@ bool rep_acc_usable(const StrictArgs& a, int C) {
            round_up(a.n_r, kRowPad) * a.ldp < lim;
 }
 
-bool rep_acc_supported(int R, int C, int W, int U) {
-#define AFMM_CASE(r, c, w, u) \
-    if (R == r && C == c && W == w && U == u) return true;
+bool rep_acc_supported(int R, int C, int W, int U, int KP) {
+#define AFMM_CASE(r, c, w, u, kp) \
+    if (R == r && C == c && W == w && U == u && KP == kp) return true;
     AFMM_ACC_CONFIGS(AFMM_CASE)
 #undef AFMM_CASE
     return false;
 }
 
 hipError_t launch_rep_acc(const StrictArgs& a, const AccLists& L, int R, int C, int W, int U,
-                          hipStream_t s) {
-#define AFMM_CASE(r, c, w, u) \
-    if (R == r && C == c && W == w && U == u) return launch_acc<r, c, w, u>(a, L, s);
+                          int KP, hipStream_t s) {
+#define AFMM_CASE(r, c, w, u, kp) \
+    if (R == r && C == c && W == w && U == u && KP == kp) return launch_acc<r, c, w, u, kp>(a, L, s);
     AFMM_ACC_CONFIGS(AFMM_CASE)
 #undef AFMM_CASE
     return hipErrorInvalidValue;

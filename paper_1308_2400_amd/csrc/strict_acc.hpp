@@ -19,8 +19,8 @@ AccLists acc_lists_at(uint8_t* p, int n_c, int n_k, int C);
 hipError_t launch_compact_base(const float* Q, int64_t ldq, int n_k, int n_c, int C,
                                const AccLists& L, hipStream_t s);
 hipError_t launch_rep_acc(const StrictArgs& a, const AccLists& L, int R, int C, int W, int U,
-                          hipStream_t s);
-bool rep_acc_supported(int R, int C, int W, int U);
+                          int KP, hipStream_t s);
+bool rep_acc_supported(int R, int C, int W, int U, int KP);
 bool rep_acc_usable(const StrictArgs& a, int C);  // 31-bit buffer offsets
 
 }  // namespace afmm

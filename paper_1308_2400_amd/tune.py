@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 
 CANDIDATES = [(m, r, c, w, u, kp) for m in (0, 2, 3, 4) for r in (1, 2, 4, 6, 8, 16)
-              for c in (1, 2, 4, 8, 16) for w in (4, 8, 16) for u in (1, 2, 4) for kp in (4, 8, 16)]
+              for c in (1, 2, 4, 8, 16, 32, 64) for w in (4, 8, 16) for u in (1, 2, 4)
+              for kp in (4, 8, 16)]
 
 
 def _inputs(case, n, seed):

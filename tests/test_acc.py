@@ -3,7 +3,8 @@
 The form lists each k's non-zero bases per band of lane columns and keeps the Z
 block in LDS; it must give the oracle's bits exactly like every other form.  Cases
 cover ragged sizes, real-factor densities from 2 % (C5-like) to 100 % (segments
-longer than 64 entries, walked in several chunks), -0.0 bases (skipped like +0.0),
+longer than 64 entries per lane slot set, walked in several chunks; lanes with
+one, two and four slots), -0.0 bases (skipped like +0.0),
 counts of 255 and more (escape path), an all-zero real factor, and sampled rows of
 the n=16384 case-A workload.
 """
@@ -17,7 +18,9 @@ pytestmark = pytest.mark.gpu
 
 ACC = [(4, 4, 16, 8, 1, 16), (4, 4, 16, 8, 2, 16), (4, 4, 16, 8, 4, 16), (4, 2, 16, 16, 1, 16),
        (4, 2, 16, 16, 2, 16), (4, 2, 16, 16, 4, 16), (4, 4, 8, 16, 1, 16), (4, 8, 8, 8, 1, 16),
-       (4, 4, 4, 8, 1, 16)]
+       (4, 4, 4, 8, 1, 16),
+       # two and four entries per lane (bands of 2048 and 4096 columns, 8-k panels)
+       (4, 2, 32, 8, 2, 8), (4, 1, 32, 16, 2, 8), (4, 1, 64, 8, 2, 8), (4, 1, 64, 8, 1, 8)]
 
 
 @pytest.fixture(scope="module")
