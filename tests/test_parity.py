@@ -305,3 +305,34 @@ def test_workspace_caller_and_stream_ordered(dev):
     small = torch.empty(16, dtype=torch.uint8, device=dev)
     with pytest.raises(afmm.AfmmError):
         afmm.multiply("B", Xd, Yd, workspace=small)
+
+
+def test_concurrent_streams(dev):
+    """Products queued alternately on two streams (default-priority, each with its own
+    workspace) run concurrently; every result equals the oracle's bits, and the split
+    form's results equal a run on its own."""
+    import torch
+    afmm = _afmm()
+    cases = [("B", 700, 41), ("A", 520, 42), ("B", 333, 43), ("A", 901, 44)]
+    host = [(c, *_rand_case(c, n, seed, int_hi=12)) for c, n, seed in cases]
+    dev_in = [(c, _to(dev, X), _to(dev, Y)) for c, X, Y in host]
+    alone = [afmm.multiply(c, Xd, Yd, mode="split_bf16x3") for c, Xd, Yd in dev_in]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for i, (c, Xd, Yd) in enumerate(dev_in):
+        s = streams[i % 2]
+        with torch.cuda.stream(s):
+            n = Xd.shape[0]
+            ws = torch.empty(afmm.workspace_size(c, n), dtype=torch.uint8, device=dev)
+            split_ws = torch.empty(afmm.workspace_size(c, n, "split_bf16x3"), dtype=torch.uint8,
+                                   device=dev)
+            outs.append((afmm.multiply(c, Xd, Yd, workspace=ws),
+                         afmm.multiply(c, Xd, Yd, mode="split_bf16x3", workspace=split_ws),
+                         ws, split_ws))
+    for s in streams:
+        s.synchronize()
+    for (c, X, Y), (Z, Zs, _, _), Za in zip(host, outs, alone):
+        Zref, _ = oracle.strict_f32(c, X, Y)
+        assert _bits_equal(Z.cpu().numpy(), Zref), c
+        assert torch.equal(Zs, Za)
