@@ -185,7 +185,18 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *            counts are fetched ahead together.  The lists take
  *            8 * round_up(lane extent, 64*C) * round_up(k, 16) bytes of
  *            workspace (afmm_workspace_size_config); falls back to 0 when one
- *            band of them or the count bytes exceed 2^31 bytes.
+ *            band of them or the count bytes exceed 2^31 bytes,
+ *            7 = over the non-zeros of both factors, for the low-density regime
+ *            of Section 2.2 (d1 * d2 ~ 1/n, additions ~ n^2): passes list the
+ *            non-zero entries of X's rows and of Y's rows (per band of 64*C
+ *            columns); a workgroup keeps W rows x 64*C columns of Z in LDS,
+ *            a wave walks its row's X list in ascending k and, for each k,
+ *            its lanes take Y's list for that k (case B: the count is the
+ *            wave's, the base the lane's; case A: the other way round, each
+ *            lane looping its own count).  Work is proportional to the
+ *            pairs of non-zero entries; R = 1, U = 1, k_panel 16 only.
+ *            Lists: 8 * (m * round_up(k, 64) + k * round_up(n, 64*C)) bytes
+ *            plus lengths (afmm_workspace_size_config).
  *   rows_per_wave R, cols_per_lane C, waves per workgroup W, unroll U (1
  *   or 2: the repetition loop does U additions per trip; 4, mapping 4
  *   only: one, two and four additions under tests of the count's low bits,

@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "strict_acc.hpp"
+#include "strict_rows.hpp"
 
 static int& g_last_hip_error_slot() {
     static thread_local int e = 0;
@@ -117,6 +118,14 @@ struct StrictLayout {
 // non-zero bases.
 StrictLayout strict_layout(afmm_case c, const Shape& p, const afmm_config& cfg) {
     StrictLayout L;
+    if (cfg.mapping == 7) {
+        // only the row lists of both factors
+        L.rows_pad = 0;
+        L.ldp = L.ldq = 0;
+        L.p8 = L.xt = L.esc = L.acc = 0;
+        L.total = rows_lists_bytes((int)p.m, (int)p.k, (int)p.n, cfg.cols_per_lane);
+        return L;
+    }
     L.rows_pad = (int)round_up(c == AFMM_CASE_B ? p.m : p.n, kRowPad);
     L.ldp = round_up(p.k, kKPad);
     L.ldq = round_up(p.m, 64);
@@ -198,6 +207,7 @@ bool config_ok(afmm_case c, const afmm_config& g) {
         return rep_sparse_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (g.mapping == 4)
         return rep_acc_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
+    if (g.mapping == 7) return rep_rows_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (kp != 16) return false;
     if (u != 1) return false;
     if (g.mapping == 1)
@@ -235,6 +245,16 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
     Scratch sc;
     const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
     if (st != AFMM_OK) return st;
+    if (cfg.mapping == 7) {
+        const int cid = c == AFMM_CASE_A ? 0 : 1;
+        const RowsLists lists =
+            rows_lists_at(sc.at(0), (int)p.m, (int)p.k, (int)p.n, cfg.cols_per_lane);
+        AFMM_HIP(launch_compact_rows(cid, X, p.ldx, Y, p.ldy, (int)p.m, (int)p.k, (int)p.n,
+                                     cfg.cols_per_lane, lists, s));
+        AFMM_HIP(launch_rep_rows(cid, (int)p.m, (int)p.k, (int)p.n, lists, Z, p.ldz,
+                                 cfg.cols_per_lane, cfg.waves, s));
+        return AFMM_OK;
+    }
     uint8_t* P8 = sc.at(L.p8);
     uint32_t* esc = reinterpret_cast<uint32_t*>(sc.at(L.esc));
     StrictArgs a{};

@@ -1,0 +1,214 @@
+// Strict AFMM kernel over the non-zeros of both factors (mapping 7; Section 2,
+// bit-exact binary32 repeated addition), for the low-density regime of Section
+// 2.2 where d1 * d2 ~ 1/n and the additions grow as n^2.
+//
+// Two compaction passes list, for every row i of X, its entries with a non-zero
+// base or a positive count ({value bits, k}, ascending k), and for every row k
+// of Y and band of 64*C columns, its entries likewise ({value bits, column in
+// the band}).  A workgroup keeps W rows x 64*C columns of Z in LDS; wave w owns
+// row i and walks X's list for i in ascending k; for each k its lanes take Y's
+// list for (k, band), 64 entries at a time, read Z[i][j] from LDS, add the base
+// the count's number of times and write it back.  Case B: the count X[i,k] is
+// the same for the whole wave and the base Y[k,j] differs per lane; case A: the
+// base X[i,k] is the wave's and the count Y[k,j] the lane's (a lane loops its own
+// count).  Every element receives its additions in ascending k, a k's
+// repetitions consecutively, so the bits are those of the sequential loops; the
+// work is proportional to the number of (i,k,j) with both entries non-zero.
+#include "strict_rows.hpp"
+
+namespace afmm {
+
+size_t rows_lists_bytes(int m, int kd, int n, int C) {
+    const int64_t ct = (int64_t)kWave * C;
+    const int64_t xcap = round_up(kd, kWave), bands = (n + ct - 1) / ct;
+    return (size_t)round_up((int64_t)m * xcap * 8, 256) + (size_t)round_up((int64_t)m * 4, 256) +
+           (size_t)round_up(bands * kd * ct * 8, 256) + (size_t)round_up(bands * kd * 4, 256);
+}
+
+RowsLists rows_lists_at(uint8_t* p, int m, int kd, int n, int C) {
+    const int64_t ct = (int64_t)kWave * C;
+    const int64_t xcap = round_up(kd, kWave), bands = (n + ct - 1) / ct;
+    RowsLists L;
+    L.xcap = xcap;
+    L.xent = reinterpret_cast<uint2*>(p);
+    p += round_up((int64_t)m * xcap * 8, 256);
+    L.xlen = reinterpret_cast<int32_t*>(p);
+    p += round_up((int64_t)m * 4, 256);
+    L.yent = reinterpret_cast<uint2*>(p);
+    p += round_up(bands * kd * ct * 8, 256);
+    L.ylen = reinterpret_cast<int32_t*>(p);
+    return L;
+}
+
+// One wave per segment (band, row): the entries of M[row][band*ct, band*ct + ct)
+// that take part in an addition (INT: count > 0; otherwise base != 0, so -0.0
+// is dropped and NaN kept), ascending column, at their rank.
+template <bool INT>
+__global__ __launch_bounds__(256) void compact_rows_kernel(const uint32_t* __restrict__ M,
+                                                           int64_t ld, int rows, int cols, int ct,
+                                                           int64_t n_segs, uint2* __restrict__ ent,
+                                                           int32_t* __restrict__ lens) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (seg >= n_segs) return;  // whole waves
+    const int band = (int)(seg / rows);
+    const int row = (int)(seg - (int64_t)band * rows);
+    const uint32_t* __restrict__ src = M + (int64_t)row * ld + (int64_t)band * ct;
+    const int width = min(ct, cols - band * ct);
+    uint2* __restrict__ out = ent + seg * ct;
+    int count = 0;
+    for (int ch = 0; ch < width; ch += kWave) {
+        const int c = ch + lane;
+        const uint32_t v = c < width ? src[c] : 0u;
+        const bool take = c < width && (INT ? (int32_t)v > 0 : __uint_as_float(v) != 0.0f);
+        const uint64_t mk = __ballot(take);
+        if (take) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            out[count + (int)below] = make_uint2(v, (uint32_t)c);
+        }
+        count += __popcll(mk);
+    }
+    if (lane == 0) lens[seg] = count;
+}
+
+template <bool INT>
+hipError_t launch_compact(const void* M, int64_t ld, int rows, int cols, int ct, uint2* ent,
+                          int32_t* lens, hipStream_t s) {
+    const int64_t bands = (cols + ct - 1) / ct;
+    const int64_t n_segs = bands * rows;
+    hipLaunchKernelGGL(compact_rows_kernel<INT>, dim3((unsigned)((n_segs + 3) / 4)), dim3(256), 0,
+                       s, static_cast<const uint32_t*>(M), ld, rows, cols, ct, n_segs, ent, lens);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_rows(int case_id, const void* X, int64_t ldx, const void* Y,
+                               int64_t ldy, int m, int kd, int n, int C, const RowsLists& L,
+                               hipStream_t s) {
+    const bool x_int = case_id == 1;  // case B: X holds the counts
+    // X: one band as wide as its row (capacity xcap)
+    hipError_t e = x_int ? launch_compact<true>(X, ldx, m, kd, (int)L.xcap, L.xent, L.xlen, s)
+                         : launch_compact<false>(X, ldx, m, kd, (int)L.xcap, L.xent, L.xlen, s);
+    if (e != hipSuccess) return e;
+    return x_int ? launch_compact<false>(Y, ldy, kd, n, kWave * C, L.yent, L.ylen, s)
+                 : launch_compact<true>(Y, ldy, kd, n, kWave * C, L.yent, L.ylen, s);
+}
+
+template <int C, int W>
+struct RowsTile {
+    static constexpr int CT = kWave * C;   // columns per block (one band)
+    static constexpr int STRIDE = CT + 1;  // LDS row pitch in floats
+    static constexpr int LDS_FLOATS = W * STRIDE;
+    static_assert(LDS_FLOATS * 4 <= 160 * 1024, "the Z rows must fit in LDS");
+};
+
+template <int C, int W, bool CASE_A>
+__global__ __launch_bounds__(W * kWave) void rep_rows_kernel(
+    int m, int kd, int n, const uint2* __restrict__ xent, const int32_t* __restrict__ xlen,
+    int64_t xcap, const uint2* __restrict__ yent, const int32_t* __restrict__ ylen,
+    float* __restrict__ Z, int64_t ldz, int n_row_blocks, int n_tiles) {
+    using T = RowsTile<C, W>;
+    __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    const int t = xcd_remap(blockIdx.x, n_tiles);
+    const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int i = rb * W + wave;
+    const int c0 = band * T::CT;
+    float* zrow = lds + wave * T::STRIDE;
+
+    for (int q = threadIdx.x; q < T::LDS_FLOATS; q += W * kWave) lds[q] = 0.0f;  // Z = +0.0
+    __syncthreads();
+
+    if (i < m) {
+        const uint2* __restrict__ xl = xent + (int64_t)i * xcap;
+        const int nx = xlen[i];
+        const uint2* __restrict__ yb = yent + (int64_t)band * kd * T::CT;
+        const int32_t* __restrict__ yl = ylen + (int64_t)band * kd;
+        for (int xc = 0; xc < nx; xc += kWave) {
+            // 64 of row i's entries, one per lane; taken one at a time below
+            const uint2 xe = xc + lane < nx ? xl[xc + lane] : make_uint2(0u, 0u);
+            const int cnt = min(kWave, nx - xc);
+            // entry 0's list: its length and first 64 entries, fetched ahead
+            int k = __builtin_amdgcn_readlane((int)xe.y, 0);
+            int len = yl[k];
+            uint2 ye = yb[(int64_t)k * T::CT + lane];
+            for (int e = 0; e < cnt; ++e) {
+                const uint32_t xv = (uint32_t)__builtin_amdgcn_readlane((int)xe.x, e);
+                const int k_cur = k, len_cur = len;
+                const uint2 ye_cur = ye;
+                if (e + 1 < cnt) {  // the next entry's list goes out before this one's work
+                    k = __builtin_amdgcn_readlane((int)xe.y, e + 1);
+                    len = yl[k];
+                    ye = yb[(int64_t)k * T::CT + lane];
+                }
+                for (int yc = 0; yc < len_cur; yc += kWave) {
+                    const uint2 y = yc == 0 ? ye_cur : yb[(int64_t)k_cur * T::CT + yc + lane];
+                    if (lane < len_cur - yc) {
+                        const int j = (int)y.y;
+                        float z = zrow[j];
+                        if (CASE_A) {
+                            // base X[i,k] for the wave, count Y[k,j] for the lane
+                            const float base = __uint_as_float(xv);
+                            for (int32_t r = (int32_t)y.x; r > 0; --r) z = z + base;
+                        } else {
+                            // count X[i,k] for the wave, base Y[k,j] for the lane
+                            const float base = __uint_as_float(y.x);
+                            for (int32_t r = (int32_t)xv; r > 0; --r) z = z + base;
+                        }
+                        zrow[j] = z;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < W * T::CT; q += W * kWave) {
+        const int r = q / T::CT, c = q - r * T::CT;
+        const int row = rb * W + r;
+        if (row < m && c0 + c < n) Z[(int64_t)row * ldz + c0 + c] = lds[r * T::STRIDE + c];
+    }
+}
+
+template <int C, int W>
+hipError_t launch_rows(int case_id, int m, int kd, int n, const RowsLists& L, float* Z,
+                       int64_t ldz, hipStream_t s) {
+    using T = RowsTile<C, W>;
+    const int n_row_blocks = (m + W - 1) / W;
+    const int n_tiles = n_row_blocks * ((n + T::CT - 1) / T::CT);
+    dim3 grid(n_tiles), block(W * kWave);
+    if (case_id == 0)
+        hipLaunchKernelGGL((rep_rows_kernel<C, W, true>), grid, block, 0, s, m, kd, n, L.xent,
+                           L.xlen, L.xcap, L.yent, L.ylen, Z, ldz, n_row_blocks, n_tiles);
+    else
+        hipLaunchKernelGGL((rep_rows_kernel<C, W, false>), grid, block, 0, s, m, kd, n, L.xent,
+                           L.xlen, L.xcap, L.yent, L.ylen, Z, ldz, n_row_blocks, n_tiles);
+    return hipGetLastError();
+}
+
+// (C, W): W rows x 64*C columns of Z in LDS per workgroup
+#define AFMM_ROWS_CONFIGS(X) \
+    X(64, 8)                 \
+    X(32, 16)                \
+    X(16, 16)                \
+    X(16, 8)
+
+bool rep_rows_supported(int R, int C, int W, int U, int KP) {
+    if (R != 1 || U != 1 || KP != 16) return false;
+#define AFMM_CASE(c, w) \
+    if (C == c && W == w) return true;
+    AFMM_ROWS_CONFIGS(AFMM_CASE)
+#undef AFMM_CASE
+    return false;
+}
+
+hipError_t launch_rep_rows(int case_id, int m, int kd, int n, const RowsLists& L, float* Z,
+                           int64_t ldz, int C, int W, hipStream_t s) {
+#define AFMM_CASE(c, w) \
+    if (C == c && W == w) return launch_rows<c, w>(case_id, m, kd, n, L, Z, ldz, s);
+    AFMM_ROWS_CONFIGS(AFMM_CASE)
+#undef AFMM_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace afmm

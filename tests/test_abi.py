@@ -121,7 +121,9 @@ def test_config_table(afmm):
     assert afmm.config_supported("B", (3, 4, 8, 16, 2, 16))
     assert not afmm.config_supported("B", (3, 2, 16, 16, 1, 16))  # 128 KB of LDS: not built
     assert afmm.config_supported("A", (4, 4, 16, 8, 1, 16))  # compacted-base variant
-    assert not afmm.config_supported("A", (4, 4, 16, 8, 1, 8))  # 16-k count words only
+    assert not afmm.config_supported("A", (4, 4, 16, 8, 1, 8))  # not instantiated
+    assert afmm.config_supported("B", (7, 1, 16, 16, 1, 16))  # row lists of both factors
+    assert not afmm.config_supported("B", (7, 2, 16, 16, 1, 16))  # one row per wave only
     afmm.set_tuning([])
     builtin = afmm.default_config("B", 4096)
     afmm.set_tuning([("B", 1000, 5000, (0, 4, 4, 4))])

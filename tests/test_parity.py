@@ -80,7 +80,8 @@ CONFIGS = [(0, 8, 8, 8), (0, 8, 8, 8, 2), (0, 4, 8, 8), (0, 8, 4, 8), (0, 8, 4, 
            (3, 2, 16, 16, 1, 8), (3, 2, 16, 16, 2, 8), (3, 4, 8, 16, 1, 16), (3, 4, 8, 16, 2, 16),
            (3, 2, 8, 16, 2, 16), (3, 2, 16, 8, 1, 4), (3, 2, 16, 8, 2, 4), (3, 1, 16, 16, 1, 8),
            (4, 4, 16, 8, 1, 16), (4, 4, 16, 8, 2, 16), (4, 2, 16, 16, 1, 16), (4, 4, 8, 16, 1, 16),
-           (4, 8, 8, 8, 1, 16), (4, 4, 4, 8, 1, 16), (4, 2, 32, 8, 2, 8), (4, 1, 64, 8, 2, 8)]
+           (4, 8, 8, 8, 1, 16), (4, 4, 4, 8, 1, 16), (4, 2, 32, 8, 2, 8), (4, 1, 64, 8, 2, 8),
+           (7, 1, 64, 8, 1, 16), (7, 1, 16, 16, 1, 16)]
 SPARSE = [c for c in CONFIGS if c[0] == 3]
 
 

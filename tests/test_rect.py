@@ -69,7 +69,8 @@ def test_rect_strict_bitexact(dev, case, shape):
 
 CFGS = [(0, 4, 16, 16, 1, 16), (0, 4, 16, 16, 2, 16), (0, 2, 1, 4, 1, 16), (0, 4, 2, 4, 2, 16), (2, 8, 8, 4),
         (3, 2, 16, 16, 1, 8), (3, 2, 8, 16, 2, 16), (3, 1, 16, 16, 1, 8), (4, 4, 16, 8, 1, 16),
-        (4, 4, 4, 8, 1, 16), (4, 2, 32, 8, 2, 8), (4, 1, 64, 8, 2, 8)]
+        (4, 4, 4, 8, 1, 16), (4, 2, 32, 8, 2, 8), (4, 1, 64, 8, 2, 8), (7, 1, 64, 8, 1, 16),
+        (7, 1, 16, 16, 1, 16)]
 
 
 @pytest.mark.parametrize("case", ["A", "B"])

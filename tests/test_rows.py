@@ -1,0 +1,103 @@
+"""GPU parity of the strict form over the non-zeros of both factors (mapping 7)
+against the CPU oracle.
+
+The form lists the non-zero entries of X's rows and of Y's rows (per band of
+columns) and walks, for each row of Z, X's list in ascending k and Y's list of
+each such k; it must give the oracle's bits exactly like every other form.  Cases
+cover ragged sizes, densities from 1 % to 100 % (Y lists longer than 64 entries),
+-0.0 bases, counts of 255 and more and negative counts (no additions), an all-zero
+factor, and sampled rows in the low-density regime d1 * d2 = 1/n at n = 4096.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+ROWS = [(7, 1, 64, 8, 1, 16), (7, 1, 32, 16, 1, 16), (7, 1, 16, 16, 1, 16), (7, 1, 16, 8, 1, 16)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    import paper_1308_2400_amd  # noqa: F401  (fails loudly when libafmm.so is missing)
+    return torch.device("cuda:0")
+
+
+def _afmm():
+    import paper_1308_2400_amd
+    return paper_1308_2400_amd
+
+
+def _to(dev, a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def _inputs(case, n, seed, d_real, d_int, int_lo=0, int_hi=6):
+    r = np.random.default_rng(seed)
+    real = r.uniform(-1, 1, (n, n)).astype(np.float32)
+    real[r.random((n, n)) > d_real] = 0
+    real[(real == 0) & (r.random((n, n)) < 0.5)] = -0.0
+    ints = r.integers(int_lo, int_hi + 1, (n, n)).astype(np.int32)
+    ints[r.random((n, n)) > d_int] = 0
+    return (real, ints) if case == "A" else (ints, real)
+
+
+def _check_all(dev, case, X, Y, configs=ROWS):
+    afmm = _afmm()
+    Zref, _ = oracle.strict_f32(case, X, Y)
+    Xd, Yd = _to(dev, X), _to(dev, Y)
+    for cfg in configs:
+        assert afmm.config_supported(case, cfg), cfg
+        Z = afmm.multiply(case, Xd, Yd, "strict", config=cfg).cpu().numpy()
+        d = np.argwhere(_bits(Z) != _bits(Zref))
+        if len(d):
+            pytest.fail(f"{cfg}: {len(d)} elements differ, first {tuple(d[0])}")
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("n", [1, 7, 130, 515, 1100])
+def test_rows_sizes_and_densities(dev, case, n):
+    for d_real, d_int in ((0.01, 0.05), (0.3, 0.7), (1.0, 1.0)):
+        X, Y = _inputs(case, n, 700 + n + int(100 * d_real), d_real, d_int)
+        _check_all(dev, case, X, Y)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_rows_large_and_negative_counts(dev, case):
+    """Counts up to 400 (no byte packing here: the lists hold the int32) and
+    negative counts, which add nothing."""
+    X, Y = _inputs(case, 260, 77, 0.2, 0.3, int_lo=-50, int_hi=400)
+    _check_all(dev, case, X, Y)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_rows_zero_factor(dev, case):
+    afmm = _afmm()
+    for d_real, d_int in ((0.0, 0.5), (0.5, 0.0)):
+        X, Y = _inputs(case, 200, 3, d_real, d_int)
+        Z = afmm.multiply(case, _to(dev, X), _to(dev, Y), "strict", config=ROWS[0]).cpu().numpy()
+        assert (_bits(Z) == 0).all()
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_rows_quadratic_regime_sampled(dev, case):
+    """n = 4096 with both densities 1/64 (d1 * d2 = 1/n): sampled rows bit-exact."""
+    n, d = 4096, 1.0 / 64
+    real_spec = gen.RealSpec(gen.UNIFORMPM1, d)
+    int_spec = gen.IntSpec(gen.INT_UNIFORM, d, 1, 7)
+    w = gen.Workload(f"quad_{case}", case, n, real_spec, int_spec, 9100 + (case == "B"))
+    X, Y = w.X(), w.Y()
+    afmm = _afmm()
+    Z = afmm.multiply(case, _to(dev, X), _to(dev, Y), "strict", config=ROWS[0]).cpu().numpy()
+    rows = [0, 17, 2048, 4095]
+    Zr, _ = oracle.strict_f32(case, X[rows], Y, rows=rows, x_rows_only=True)
+    assert np.array_equal(_bits(Z[rows]), _bits(Zr))
