@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -40,6 +41,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--table1", action="store_true",
                    help="run the paper's Table 1 parameter grid (case A) instead of the benchmark")
+    p.add_argument("--lowdensity", action="store_true",
+                   help="run Section 2.2's low-density regime (d1*d2 = 1/n, n = 1024..8192) "
+                        "instead of the benchmark")
     p.add_argument("--c5", action="store_true",
                    help="run the case-A n=16384 workload (strict vs split, sampled-row checks) "
                         "instead of the benchmark")
@@ -309,6 +313,68 @@ def table1(args):
     print(json.dumps(out), flush=True)
 
 
+# the form over the non-zeros of both factors (mapping 7): 16 waves, 2048-column bands
+LOW_DENSITY_CONFIG = (7, 1, 32, 16, 1, 16)
+LOW_DENSITY_N = (1024, 2048, 4096, 8192)
+
+
+def low_density(args):
+    """Section 2.2's low-density regime: d1 * d2 = 1/n (both densities n^-1/2), case A
+    and case B, integer non-zeros U{1..7}, real ones U(-1,1).  The additions grow as n^2;
+    the default strict form walks every k of every row block, the form over the
+    non-zeros of both factors does work in proportion to the non-zero pairs.  Two rows
+    per product checked bit for bit against the oracle; growth exponents fitted."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_1308_2400_amd as afmm
+    stream = torch.cuda.current_stream()
+    rows = []
+    for case in ("A", "B"):
+        for n in LOW_DENSITY_N:
+            d = 1.0 / math.sqrt(n)
+            w = gen.Workload(f"lowdensity_{case}_n{n}", case, n, gen.RealSpec(gen.UNIFORMPM1, d),
+                             gen.IntSpec(gen.INT_UNIFORM, d, 1, 7), gen.SEED0 + 7,
+                             n + (1 if case == "B" else 0))
+            X, Y = w.X(), w.Y()
+            Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+            adds = afmm.count_adds(case, Xd, Yd)
+            steps = max(args.steps, 3)
+            Zd = afmm.multiply(case, Xd, Yd)
+            ms_default = event_time_ms(lambda: afmm.multiply(case, Xd, Yd, out=Zd), steps, stream)
+            Zl = afmm.multiply(case, Xd, Yd, config=LOW_DENSITY_CONFIG)
+            ms_low = event_time_ms(
+                lambda: afmm.multiply(case, Xd, Yd, out=Zl, config=LOW_DENSITY_CONFIG), steps,
+                stream)
+            sample = [n // 3, n - 1]
+            Zr, _ = oracle.strict_f32(case, X[sample], Y, rows=sample, x_rows_only=True)
+            ok = bool(np.array_equal(Zl.cpu().numpy()[sample].view(np.uint32), Zr.view(np.uint32))
+                      and torch.equal(Zl.view(torch.int32), Zd.view(torch.int32)))
+            rows.append({"case": case, "n": n, "d1": d, "d2": d, "adds": adds,
+                         "default_ms": ms_default,
+                         "default_config": list(afmm.default_config(case, n)),
+                         "low_density_ms": ms_low, "speedup": ms_default / ms_low,
+                         "bitexact_sampled_rows": ok})
+            log(f"lowdensity {case} n={n}: {adds:.3e} adds, default {ms_default:.3f} ms, "
+                f"low-density form {ms_low:.3f} ms")
+            del Xd, Yd, Zd, Zl
+            torch.cuda.empty_cache()
+
+    def exponent(case, key):
+        sel = [r for r in rows if r["case"] == case]
+        return float(np.polyfit(np.log([r["n"] for r in sel]), np.log([r[key] for r in sel]),
+                                1)[0])
+    fits = {case: {k: exponent(case, k) for k in ("adds", "default_ms", "low_density_ms")}
+            for case in ("A", "B")}
+    out = {"metric": "low-density regime d1*d2 = 1/n: strict AFMM time per product", "unit": "ms",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded generator)",
+           "low_density_config": list(LOW_DENSITY_CONFIG), "growth_exponents_in_n": fits,
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -316,6 +382,8 @@ def main():
               "(the product shards by rows with no exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.lowdensity:
+        return low_density(args)
     if args.table1:
         return table1(args)
     if args.c5:
