@@ -226,6 +226,17 @@ afmm_config afmm_default_config(afmm_case c, int64_t n);
  * compiled); afmm_workspace_size covers the configuration the library picks. */
 size_t afmm_workspace_size_config(afmm_case c, int64_t n, const afmm_config *cfg);
 
+/* A configuration for the strict n x n product of these operands, chosen from
+ * the densities of the two factors, counted on the device (the call waits for
+ * `stream`): with d_real the fraction of non-zero real entries and d_int that
+ * of positive counts, the form over the non-zeros of both factors (mapping 7)
+ * when d_real * d_int * n <= 24, else the compacted-base form (mapping 4) when
+ * d_real <= 0.06, otherwise afmm_default_config (also for n < 1024).  The
+ * thresholds come from measurements on MI355X; every configuration gives the
+ * same bits.  For callers that know nothing of their data's sparsity. */
+afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void *X, const void *Y,
+                                hipStream_t stream, afmm_config *out);
+
 /* Strict product with an explicit configuration (for the autotuner). */
 afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void *X, const void *Y,
                                         float *Z, const afmm_config *cfg, void *workspace,

@@ -67,6 +67,7 @@ _SIGS = {
     "afmm_config_supported": ([_ci, ctypes.POINTER(afmm_config)], _ci),
     "afmm_default_config": ([_ci, _i64], afmm_config),
     "afmm_workspace_size_config": ([_ci, _i64, ctypes.POINTER(afmm_config)], _sz),
+    "afmm_suggest_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config)], _ci),
     "afmm_multiply_strict_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config), _vp,
                                      _sz, _vp], _ci),
     "afmm_set_tuning": ([_i32, _vp, _vp, _vp, _vp], _ci),
@@ -259,6 +260,18 @@ def default_config(case, n):
     """(mapping, R, C, W, unroll, k_panel) the library uses for a strict product of this
     size (tuning table, else the built-in rule)."""
     return _lib.afmm_default_config(_case_id(case), n).as_tuple()
+
+
+def suggest_config(case, X, Y):
+    """Configuration for the strict square product of (X, Y) chosen from the factors'
+    densities (counted on the device; synchronises)."""
+    c, m, k, n, ldx, ldy = _shape(case, X, Y)
+    if not _square(m, k, n, ldx, ldy):
+        raise ValueError("suggest_config takes square contiguous operands")
+    out = afmm_config()
+    _check("suggest_config", _lib.afmm_suggest_config(c, n, X.data_ptr(), Y.data_ptr(), _stream(),
+                                                      ctypes.byref(out)))
+    return out.as_tuple()
 
 
 def _cfg(cfg):

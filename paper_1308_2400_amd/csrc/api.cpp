@@ -481,6 +481,41 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, 
     return AFMM_OK;
 }
 
+afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void* X, const void* Y,
+                                hipStream_t stream, afmm_config* out) {
+    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !out || (c != AFMM_CASE_A && c != AFMM_CASE_B))
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    *out = afmm_default_config(c, n);
+    if (n < 1024) return AFMM_OK;  // below this the size-keyed choice holds for any density
+    void* buf = nullptr;
+    hipError_t e = hipMallocAsync(&buf, 16, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    uint64_t* cnt = static_cast<uint64_t*>(buf);
+    uint64_t h[2] = {0, 0};
+    const void* real = c == AFMM_CASE_A ? X : Y;
+    const void* ints = c == AFMM_CASE_A ? Y : X;
+    e = hipMemsetAsync(cnt, 0, 16, stream);
+    if (e == hipSuccess) e = launch_count_nonzero(false, real, n, (int)n, (int)n, cnt, stream);
+    if (e == hipSuccess) e = launch_count_nonzero(true, ints, n, (int)n, (int)n, cnt + 1, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, cnt, 16, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFreeAsync(buf, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    const double nn = (double)n * (double)n;
+    const double d_real = (double)h[0] / nn, d_int = (double)h[1] / nn;
+    // thresholds from measurements on MI355X (n = 2048..16384): the row-list form
+    // while a row meets few non-zero pairs per k (d_real * d_int * n, its work per
+    // k of a row, is at most 24), the compacted-base form when the real factor
+    // alone is very sparse, the size-keyed choice otherwise
+    if (d_real * d_int * (double)n <= 24.0)
+        *out = afmm_config{7, 1, n <= 2896 ? 16 : 32, 16, 1, 16};
+    else if (d_real <= 0.06)
+        *out = n <= 2896 ? afmm_config{4, 1, 64, 8, 2, 8} : afmm_config{4, 2, 32, 8, 2, 8};
+    return AFMM_OK;
+}
+
 int afmm_config_supported(afmm_case c, const afmm_config* cfg) {
     if (!cfg || (c != AFMM_CASE_A && c != AFMM_CASE_B)) return 0;
     return config_ok(c, *cfg) ? 1 : 0;

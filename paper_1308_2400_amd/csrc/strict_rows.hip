@@ -16,6 +16,8 @@
 // work is proportional to the number of (i,k,j) with both entries non-zero.
 #include "strict_rows.hpp"
 
+#include <algorithm>
+
 namespace afmm {
 
 size_t rows_lists_bytes(int m, int kd, int n, int C) {
@@ -209,6 +211,43 @@ hipError_t launch_rep_rows(int case_id, int m, int kd, int n, const RowsLists& L
     AFMM_ROWS_CONFIGS(AFMM_CASE)
 #undef AFMM_CASE
     return hipErrorInvalidValue;
+}
+
+// Entries of a rows x cols matrix (leading dimension ld) that take part in an
+// addition (INT: count > 0; otherwise base != 0), summed into *out (cleared by
+// the caller).
+template <bool INT>
+__global__ __launch_bounds__(256) void count_nonzero_kernel(const uint32_t* __restrict__ M,
+                                                            int64_t ld, int rows, int cols,
+                                                            unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long c = 0;
+    const int64_t total = (int64_t)rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t r = e / cols, col = e - r * cols;
+        const uint32_t v = M[r * ld + col];
+        c += (INT ? (int32_t)v > 0 : __uint_as_float(v) != 0.0f) ? 1u : 0u;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if (lane == 0) part[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+hipError_t launch_count_nonzero(bool is_int, const void* M, int64_t ld, int rows, int cols,
+                                uint64_t* out, hipStream_t s) {
+    const int64_t total = (int64_t)rows * cols;
+    const int blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + 255) / 256));
+    auto* o = reinterpret_cast<unsigned long long*>(out);
+    if (is_int)
+        hipLaunchKernelGGL(count_nonzero_kernel<true>, dim3(blocks), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(M), ld, rows, cols, o);
+    else
+        hipLaunchKernelGGL(count_nonzero_kernel<false>, dim3(blocks), dim3(256), 0, s,
+                           static_cast<const uint32_t*>(M), ld, rows, cols, o);
+    return hipGetLastError();
 }
 
 }  // namespace afmm

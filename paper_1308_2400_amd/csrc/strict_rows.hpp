@@ -27,4 +27,9 @@ hipError_t launch_rep_rows(int case_id, int m, int kd, int n, const RowsLists& L
                            int64_t ldz, int C, int W, hipStream_t s);
 bool rep_rows_supported(int R, int C, int W, int U, int KP);
 
+// Adds to *out (device) the number of entries of M (rows x cols, ld) that take part
+// in an addition: is_int, count > 0; otherwise base != 0.
+hipError_t launch_count_nonzero(bool is_int, const void* M, int64_t ld, int rows, int cols,
+                                uint64_t* out, hipStream_t s);
+
 }  // namespace afmm

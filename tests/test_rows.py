@@ -101,3 +101,27 @@ def test_rows_quadratic_regime_sampled(dev, case):
     rows = [0, 17, 2048, 4095]
     Zr, _ = oracle.strict_f32(case, X[rows], Y, rows=rows, x_rows_only=True)
     assert np.array_equal(_bits(Z[rows]), _bits(Zr))
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_suggested_configuration(dev, case):
+    """afmm_suggest_config: row lists when d_real * d_int * n <= 24, compacted bases
+    when only the real factor is very sparse (<= 6 %), the size-keyed choice
+    otherwise and below n = 1024; the suggested configuration gives the default's
+    bits."""
+    afmm = _afmm()
+    n = 2048
+    for d_real, d_int, mapping in ((0.1, 0.1, 7), (0.05, 0.7, 4), (0.1, 0.5, None),
+                                   (0.9, 0.3, None)):
+        X, Y = _inputs(case, n, 40 + int(100 * d_real), d_real, d_int)
+        Xd, Yd = _to(dev, X), _to(dev, Y)
+        cfg = afmm.suggest_config(case, Xd, Yd)
+        if mapping is None:
+            assert cfg == afmm.default_config(case, n)
+        else:
+            assert cfg[0] == mapping, (d_real, d_int, cfg)
+        Z = afmm.multiply(case, Xd, Yd, config=cfg)
+        Zd = afmm.multiply(case, Xd, Yd)
+        assert np.array_equal(_bits(Z.cpu().numpy()), _bits(Zd.cpu().numpy()))
+    X, Y = _inputs(case, 512, 5, 0.05, 0.05)
+    assert afmm.suggest_config(case, _to(dev, X), _to(dev, Y)) == afmm.default_config(case, 512)
