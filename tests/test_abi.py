@@ -170,3 +170,17 @@ def test_workspace_per_config(afmm):
     finally:
         afmm.set_tuning([])
         afmm.load_tuning()
+
+
+def test_workspace_of_the_list_forms(afmm):
+    """The row-list form (mapping 7) needs only its lists: 8 bytes per element of X
+    (rows padded to 64 entries) and of Y (rows padded to the 64*C band), plus one
+    length per list; none of the count-byte or transpose space."""
+    n = 1000
+    for C in (16, 32):
+        ws = afmm.workspace_size("B", n, config=(7, 1, C, 16, 1, 16))
+        band = 64 * C
+        lists = 8 * n * 1024 + 8 * n * ((n + band - 1) // band) * band
+        assert lists <= ws <= lists + 4 * n * 2 + 4 * 256
+    # unsupported shapes of the form are not compiled
+    assert afmm.workspace_size("B", n, config=(7, 1, 24, 16, 1, 16)) == 0
