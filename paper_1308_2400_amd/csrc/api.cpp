@@ -150,8 +150,8 @@ struct SplitLayout {
 // have one row per i (case A) or per j (case B), the integer plane the other.
 SplitLayout split_layout(afmm_case c, const Shape& p) {
     SplitLayout L;
-    L.rows_real = split_rows_pad((int)(c == AFMM_CASE_A ? p.m : p.n));
-    L.rows_int = split_rows_pad((int)(c == AFMM_CASE_A ? p.n : p.m));
+    L.rows_real = split_real_rows_pad((int)(c == AFMM_CASE_A ? p.m : p.n));
+    L.rows_int = split_int_rows_pad((int)(c == AFMM_CASE_A ? p.n : p.m));
     L.ld = round_up(p.k, 64);
     Carve cv;
     for (int q = 0; q < 3; ++q) L.planes[q] = cv.take((size_t)L.rows_real * L.ld * 2);
@@ -338,14 +338,14 @@ afmm_status split_run(afmm_case c, const Shape& p, const void* X, const void* Y,
                                    P[2], L.ld, L.rows_real, s));
         AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(Y), k, n, p.ldy, true, P[3], L.ld,
                                     L.rows_int, s));
-        AFMM_HIP(launch_gemm_bf16x3(m, n, P[0], P[1], P[2], P[3], P[3], P[3], L.ld, Z, p.ldz, s));
+        AFMM_HIP(launch_gemm_bf16x3(c == AFMM_CASE_A, m, n, P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
     } else {
         // A operand: X as bf16 [i][k]; B operand: Y's three terms turned to [j][k]
         AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(X), m, k, p.ldx, false, P[3], L.ld,
                                     L.rows_int, s));
         AFMM_HIP(launch_split_real(static_cast<const float*>(Y), k, n, p.ldy, true, P[0], P[1],
                                    P[2], L.ld, L.rows_real, s));
-        AFMM_HIP(launch_gemm_bf16x3(m, n, P[3], P[3], P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
+        AFMM_HIP(launch_gemm_bf16x3(c == AFMM_CASE_A, m, n, P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
     }
     return AFMM_OK;
 }

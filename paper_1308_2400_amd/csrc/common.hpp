@@ -112,10 +112,13 @@ hipError_t launch_split_real(const float* R, int rows, int cols, int64_t ldr, bo
                              hipStream_t s);
 hipError_t launch_int_to_bf16(const int32_t* I, int rows, int cols, int64_t ldi, bool transpose,
                               uint16_t* out, int64_t ld, int rows_pad, hipStream_t s);
-hipError_t launch_gemm_bf16x3(int M, int N, const uint16_t* A0, const uint16_t* A1,
-                              const uint16_t* A2, const uint16_t* B0, const uint16_t* B1,
-                              const uint16_t* B2, int64_t ld, float* Z, int64_t ldz,
-                              hipStream_t s);
-int split_rows_pad(int n);
+// Z (M x N, pitch ldz) from the integer plane I and the term planes S0..S2
+// (hi, mid, lo), all with K pitch ld; I has one row per column of Z in case A
+// and per row of Z in case B, the term planes the other.
+hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, const uint16_t* S0,
+                              const uint16_t* S1, const uint16_t* S2, int64_t ld, float* Z,
+                              int64_t ldz, hipStream_t s);
+int split_real_rows_pad(int n);  // rows of a term plane
+int split_int_rows_pad(int n);   // rows of the integer plane
 
 }  // namespace afmm

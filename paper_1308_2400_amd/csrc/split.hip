@@ -7,14 +7,16 @@
 // 2^-100 <= |x| < 2^127).  The integer factor (0..256) is exact in bfloat16.
 // Z = sum over the three terms of (term . integer factor), contracted with
 // v_mfma_f32_32x32x16_bf16 into binary32 accumulators.  The hi products go to
-// one accumulator set and the mid/lo products to a second one; Z = hi + rest
-// at the end.  The hi products carry at most 16 significant bits, so their
-// running sum is nearly exact, and the rounding of the small mid/lo sum is
-// 2^-8 times smaller than it would be in a shared accumulator.
+// one accumulator set and the mid/lo products (lo first) to a second; Z = hi +
+// rest at the end.  The hi products carry at most 16 significant bits, so their
+// running sum is nearly exact, and the rounding of the small mid/lo sum is 2^-8
+// times smaller than it would be in a shared accumulator (one shared set would
+// round every mid/lo addition at the scale of Z: about 10x the error at n=4096,
+// growing with the square root of K).
 //
-// Operand layout: both operands K-contiguous, "A" rows = rows of Z (m),
-// "B" rows = columns of Z (n), zero padded to the tile sizes so the GEMM has
-// no bounds checks inside the K loop.
+// Operand layout: every plane is K-contiguous with one row per row of Z (the
+// factor on the left) or per column of Z (the factor on the right), zero padded
+// to the block tile so the GEMM has no bounds checks inside the K loop.
 #include "common.hpp"
 
 namespace afmm {
@@ -22,29 +24,41 @@ namespace afmm {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kGM = 128;   // tile rows (m)
-constexpr int kGN = 128;   // tile cols (n)
-constexpr int kGK = 32;    // K per LDS stage
-constexpr int kLdsRow = kGK + 8;  // bf16 per LDS row (80 B: spreads rows over banks)
+constexpr int kTI = 256;  // block rows on the integer side
+constexpr int kTS = 64;   // block rows on the split (three-term) side
+constexpr int kGK = 32;   // K per LDS stage: four 16-byte chunks per row
 
-int split_rows_pad(int n) { return (int)round_up(n, kGM); }
+int split_real_rows_pad(int n) { return (int)round_up(n, kTS); }
+int split_int_rows_pad(int n) { return (int)round_up(n, kTI); }
 
 // ---------------------------------------------------------------------------
 // Conversions (binary32 -> bfloat16, round to nearest even).
-__device__ __forceinline__ uint16_t bf16_bits_rne(float x) {
+__device__ __forceinline__ uint32_t bf16_bits_rne(float x) {
     uint32_t b = __float_as_uint(x);
-    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (uint16_t)((b >> 16) | 0x40u);
+    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return ((b >> 16) | 0x40u) & 0xFFFFu;
     b += 0x7FFFu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
+    return b >> 16;
 }
 
-__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
-    return __uint_as_float((uint32_t)h << 16);
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// A 64 x 64 block of the input goes through LDS as tile[output row][k]; the
+// write phase gives each lane eight consecutive k of one output row, so every
+// plane is written in 16-byte pieces, eight lanes to a 128-byte row segment.
+// TRANS: output row o, column k come from in[k][o]; else from in[o][k].
+// Outputs are [rows_pad x ld] with zeros outside rows x cols.
+template <bool TRANS, typename T>
+__device__ __forceinline__ void load_block(const T* __restrict__ in, int rows, int cols, int64_t ldi,
+                                           int o0, int c0, T (*tile)[65]) {
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    for (int t = ly; t < 64; t += 4) {
+        const int r = TRANS ? c0 + t : o0 + t;  // input row
+        const int c = TRANS ? o0 + lx : c0 + lx;
+        const T v = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : T(0);
+        if (TRANS) tile[lx][t] = v; else tile[t][lx] = v;
+    }
 }
 
-// out planes [rows_pad x ld] (bf16 bits) from in: rows x cols with leading
-// dimension ldi (zero outside).  Tile 64 x 64 through LDS, block (64, 4).
-// TRANS: out[c][r] = f(in[r][c]); else out[r][c] = f(in[r][c]).
 template <bool TRANS>
 __global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict__ in, int rows,
                                                         int cols, int64_t ldi,
@@ -52,27 +66,28 @@ __global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict
                                                         uint16_t* __restrict__ mid,
                                                         uint16_t* __restrict__ lo, int64_t ld) {
     __shared__ float tile[64][65];
-    const int o0 = blockIdx.x * 64;  // output row block
-    const int c0 = blockIdx.y * 64;  // output column (K) block
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    for (int t = ty; t < 64; t += 4) {
-        // TRANS: read in[c0 + t][o0 + tx] (coalesced), keep at tile[tx][t]
-        const int r = TRANS ? c0 + t : o0 + t;
-        const int c = TRANS ? o0 + tx : c0 + tx;
-        const float v = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : 0.0f;
-        if (TRANS) tile[tx][t] = v; else tile[t][tx] = v;
-    }
+    const int o0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    load_block<TRANS>(in, rows, cols, ldi, o0, c0, tile);
     __syncthreads();
-    for (int t = ty; t < 64; t += 4) {
-        const float x = tile[t][tx];
-        const uint16_t h = bf16_bits_rne(x);
-        const float r1 = x - bf16_bits_to_f32(h);
-        const uint16_t m = bf16_bits_rne(r1);
-        const float r2 = r1 - bf16_bits_to_f32(m);
-        const int64_t o = (int64_t)(o0 + t) * ld + c0 + tx;
-        hi[o] = h;
-        mid[o] = m;
-        lo[o] = bf16_bits_rne(r2);
+    for (int h = 0; h < 2; ++h) {
+        const int c = threadIdx.x + 256 * h, o = c >> 3, kq = (c & 7) * 8;
+        uint32_t ph[4], pm[4], pl[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = tile[o][kq + e];
+            const uint32_t bh = bf16_bits_rne(x);
+            const float r1 = x - bf16_bits_to_f32(bh);
+            const uint32_t bm = bf16_bits_rne(r1);
+            const uint32_t bl = bf16_bits_rne(r1 - bf16_bits_to_f32(bm));
+            const int w = e >> 1, sh = (e & 1) * 16;
+            ph[w] = (e & 1) ? ph[w] | (bh << sh) : bh;
+            pm[w] = (e & 1) ? pm[w] | (bm << sh) : bm;
+            pl[w] = (e & 1) ? pl[w] | (bl << sh) : bl;
+        }
+        const int64_t off = (int64_t)(o0 + o) * ld + c0 + kq;
+        *reinterpret_cast<uint4*>(hi + off) = make_uint4(ph[0], ph[1], ph[2], ph[3]);
+        *reinterpret_cast<uint4*>(mid + off) = make_uint4(pm[0], pm[1], pm[2], pm[3]);
+        *reinterpret_cast<uint4*>(lo + off) = make_uint4(pl[0], pl[1], pl[2], pl[3]);
     }
 }
 
@@ -82,18 +97,21 @@ __global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict
                                                       uint16_t* __restrict__ out, int64_t ld) {
     __shared__ int32_t tile[64][65];
     const int o0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    for (int t = ty; t < 64; t += 4) {
-        const int r = TRANS ? c0 + t : o0 + t;
-        const int c = TRANS ? o0 + tx : c0 + tx;
-        const int32_t v = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : 0;
-        if (TRANS) tile[tx][t] = v; else tile[t][tx] = v;
-    }
+    load_block<TRANS>(in, rows, cols, ldi, o0, c0, tile);
     __syncthreads();
-    for (int t = ty; t < 64; t += 4) {
-        const int32_t v = tile[t][tx];
-        // a count <= 0 adds nothing; 1..256 are exact in bfloat16
-        out[(int64_t)(o0 + t) * ld + c0 + tx] = v <= 0 ? (uint16_t)0 : bf16_bits_rne((float)v);
+    for (int h = 0; h < 2; ++h) {
+        const int c = threadIdx.x + 256 * h, o = c >> 3, kq = (c & 7) * 8;
+        uint32_t p[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int32_t v = tile[o][kq + e];
+            // a count <= 0 adds nothing; 1..256 are exact in bfloat16
+            const uint32_t b = v <= 0 ? 0u : bf16_bits_rne((float)v);
+            const int w = e >> 1;
+            p[w] = (e & 1) ? p[w] | (b << 16) : b;
+        }
+        *reinterpret_cast<uint4*>(out + (int64_t)(o0 + o) * ld + c0 + kq) =
+            make_uint4(p[0], p[1], p[2], p[3]);
     }
 }
 
@@ -102,11 +120,11 @@ hipError_t launch_split_real(const float* R, int rows, int cols, int64_t ldr, bo
                              hipStream_t s) {
     dim3 grid(rows_pad / 64, (unsigned)(ld / 64));
     if (transpose)
-        hipLaunchKernelGGL(split_real_kernel<true>, grid, dim3(64, 4), 0, s, R, rows, cols, ldr, hi,
+        hipLaunchKernelGGL(split_real_kernel<true>, grid, dim3(256), 0, s, R, rows, cols, ldr, hi,
                            mid, lo, ld);
     else
-        hipLaunchKernelGGL(split_real_kernel<false>, grid, dim3(64, 4), 0, s, R, rows, cols, ldr,
-                           hi, mid, lo, ld);
+        hipLaunchKernelGGL(split_real_kernel<false>, grid, dim3(256), 0, s, R, rows, cols, ldr, hi,
+                           mid, lo, ld);
     return hipGetLastError();
 }
 
@@ -114,176 +132,189 @@ hipError_t launch_int_to_bf16(const int32_t* I, int rows, int cols, int64_t ldi,
                               uint16_t* out, int64_t ld, int rows_pad, hipStream_t s) {
     dim3 grid(rows_pad / 64, (unsigned)(ld / 64));
     if (transpose)
-        hipLaunchKernelGGL(int_bf16_kernel<true>, grid, dim3(64, 4), 0, s, I, rows, cols, ldi, out,
+        hipLaunchKernelGGL(int_bf16_kernel<true>, grid, dim3(256), 0, s, I, rows, cols, ldi, out,
                            ld);
     else
-        hipLaunchKernelGGL(int_bf16_kernel<false>, grid, dim3(64, 4), 0, s, I, rows, cols, ldi, out,
+        hipLaunchKernelGGL(int_bf16_kernel<false>, grid, dim3(256), 0, s, I, rows, cols, ldi, out,
                            ld);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// GEMM: Z[m][c] = sum_k sum_s A_s[m][k] * B_s[c][k].  TRIPLE_A: three A
-// planes and one B plane (case A: the real pre-factor is split); otherwise
-// one A plane and three B planes (case B).  256 threads = 2 x 2 waves, each
-// wave a 64 x 64 block of Z = 2 x 2 MFMA 32 x 32 blocks.
+// GEMM over one 256 x 64 block of Z: 256 rows of the integer plane (the I
+// side) against 64 rows of each of the three term planes (the S side); for
+// the case-B product the I side runs along the rows of Z, for case A along its
+// columns.  256 threads = 2 x 2 waves, each wave 128 I rows x 32 S rows =
+// 4 MFMA 32 x 32 blocks, each with a hi and a mid/lo accumulator.  Per 16-wide
+// K step a wave reads 4 integer and 3 term fragments for 12 MFMAs.
 //
 // MFMA 32x32x16 operand layout: lane l supplies row (l % 32) of A (column
 // (l % 32) of B) and the eight K values 8*(l / 32) .. +7 of the 16; result
 // register v of lane l holds row 8*(v / 4) + 4*(l / 32) + v % 4, column l % 32.
-constexpr int kPlane = kGM * kLdsRow;  // bf16 per plane tile in LDS
+//
+// LDS: a stage holds the I tile (256 rows) then the three S tiles (64 rows),
+// each row 32 bf16 = four 16-byte chunks with chunk q of row r kept at slot
+// q ^ swz(r).  Fragment reads (32 consecutive rows, one chunk) and staging
+// writes (four rows, all chunks) then touch every bank once per 16 lanes.
+constexpr int kPlaneI = kTI * kGK;               // bf16 per I tile
+constexpr int kPlaneS = kTS * kGK;               // bf16 per S tile
+constexpr int kStage = kPlaneI + 3 * kPlaneS;    // 28 KB
+
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 // Tile order: each XCD gets a contiguous run of tiles (xcd_remap), and inside
-// it tiles go column-band-major in groups of kGroupM row tiles so that blocks
-// running together share both operand panels in that XCD's L2.
-constexpr int kGroupM = 8;
+// it tiles go S-band-major in groups of kGroupI I tiles so that blocks running
+// together share both operand panels in that XCD's L2.
+constexpr int kGroupI = 8;
 
-__device__ __forceinline__ void gemm_tile_coords(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
-    const int per_group = kGroupM * tiles_n;
-    const int g = t / per_group, first_m = g * kGroupM;
-    const int gm = min(tiles_m - first_m, kGroupM);
+__device__ __forceinline__ void gemm_tile_coords(int t, int tiles_i, int tiles_s, int& ti, int& ts) {
+    const int per_group = kGroupI * tiles_s;
+    const int g = t / per_group, first = g * kGroupI;
+    const int gi = min(tiles_i - first, kGroupI);
     const int r = t - g * per_group;
-    tm = first_m + r % gm;
-    tn = r / gm;
+    ti = first + r % gi;
+    ts = r / gi;
 }
 
-template <bool TRIPLE_A>
+template <bool CASE_A>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
-    int M, int N, const uint16_t* __restrict__ A0, const uint16_t* __restrict__ A1,
-    const uint16_t* __restrict__ A2, const uint16_t* __restrict__ B0,
-    const uint16_t* __restrict__ B1, const uint16_t* __restrict__ B2, int64_t ld,
-    float* __restrict__ Z, int64_t ldz, int tiles_m, int tiles_n) {
-    // LDS stage: planes 0..2 = the split side (hi, mid, lo), plane 3 = the other side
-    constexpr int STAGE = 4 * kPlane;
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * STAGE];
+    int M, int N, const uint16_t* __restrict__ I, const uint16_t* __restrict__ S0,
+    const uint16_t* __restrict__ S1, const uint16_t* __restrict__ S2, int64_t ld,
+    float* __restrict__ Z, int64_t ldz, int tiles_i, int tiles_s) {
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kStage];
 
-    int tm, tn;
-    gemm_tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, tm, tn);
-    const int m0 = tm * kGM, c0 = tn * kGN;
+    int ti, ts;
+    gemm_tile_coords(xcd_remap(blockIdx.x, tiles_i * tiles_s), tiles_i, tiles_s, ti, ts);
+    const int i0 = ti * kTI, s0 = ts * kTS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave & 1) * 64, wc = (wave >> 1) * 64;
+    const int wi = (wave & 1) * 128, wsr = (wave >> 1) * 32;
 
-    // split side rows start at s0 (m0 for TRIPLE_A, c0 otherwise); the other side at o0
-    const int s0 = TRIPLE_A ? m0 : c0, o0 = TRIPLE_A ? c0 : m0;
-    const uint16_t* S0 = TRIPLE_A ? A0 : B0;
-    const uint16_t* S1 = TRIPLE_A ? A1 : B1;
-    const uint16_t* S2 = TRIPLE_A ? A2 : B2;
-    const uint16_t* O = TRIPLE_A ? B0 : A0;
+    // Staging: thread tid moves chunk q0 of rows r0 + 64 j: four rows of the I
+    // tile and one of each S tile.  The byte offset inside a 64-row band is
+    // the same for every load (below 2^32 as ld <= 65536); the band bases are
+    // uniform.
+    const int r0 = tid >> 2, q0 = tid & 3;
+    const uint32_t goff = (uint32_t)((int64_t)r0 * ld + q0 * 8) * 2u;
+    const int64_t band = 64 * ld;  // bf16 per 64 rows
+    const char* gI = reinterpret_cast<const char*>(I + (int64_t)i0 * ld);
+    const char* gS0 = reinterpret_cast<const char*>(S0 + (int64_t)s0 * ld);
+    const char* gS1 = reinterpret_cast<const char*>(S1 + (int64_t)s0 * ld);
+    const char* gS2 = reinterpret_cast<const char*>(S2 + (int64_t)s0 * ld);
+    const int lst = r0 * kGK + ((q0 ^ swz(r0)) * 8);  // swz(r0 + 64 j) == swz(r0)
+#define AFMM_GLD(base, j, k0) \
+    (*reinterpret_cast<const uint4*>((base) + ((j) * band + (k0)) * 2 + goff))
+#define AFMM_GLOAD(g, k0)                                                          \
+    g##0 = AFMM_GLD(gI, 0, k0); g##1 = AFMM_GLD(gI, 1, k0);                         \
+    g##2 = AFMM_GLD(gI, 2, k0); g##3 = AFMM_GLD(gI, 3, k0);                         \
+    g##4 = AFMM_GLD(gS0, 0, k0); g##5 = AFMM_GLD(gS1, 0, k0); g##6 = AFMM_GLD(gS2, 0, k0);
+#define AFMM_LST(dst, plane_off, j, v) \
+    *reinterpret_cast<uint4*>((dst) + (plane_off) + (j) * 64 * kGK + lst) = (v);
+#define AFMM_LSTORE(dst, g)                                                         \
+    AFMM_LST(dst, 0, 0, g##0) AFMM_LST(dst, 0, 1, g##1)                             \
+    AFMM_LST(dst, 0, 2, g##2) AFMM_LST(dst, 0, 3, g##3)                             \
+    AFMM_LST(dst, kPlaneI, 0, g##4) AFMM_LST(dst, kPlaneI + kPlaneS, 0, g##5)        \
+    AFMM_LST(dst, kPlaneI + 2 * kPlaneS, 0, g##6)
 
-    // Global -> LDS staging: a plane tile is 128 rows x 32 K = 512 chunks of 8 bf16;
-    // thread tid moves chunks tid and tid + 256 of each of the four planes.
-    const int row_a = tid >> 2, row_b = row_a + 64, kc = (tid & 3) * 8;
-    const int64_t sa = (int64_t)(s0 + row_a) * ld + kc, sb = (int64_t)(s0 + row_b) * ld + kc;
-    const int64_t oa = (int64_t)(o0 + row_a) * ld + kc, ob = (int64_t)(o0 + row_b) * ld + kc;
-    const int la = row_a * kLdsRow + kc, lb = row_b * kLdsRow + kc;
-    uint4 g0a, g0b, g1a, g1b, g2a, g2b, goa, gob;
-#define AFMM_GLOAD(k0)                                                     \
-    g0a = *reinterpret_cast<const uint4*>(S0 + sa + (k0));                 \
-    g0b = *reinterpret_cast<const uint4*>(S0 + sb + (k0));                 \
-    g1a = *reinterpret_cast<const uint4*>(S1 + sa + (k0));                 \
-    g1b = *reinterpret_cast<const uint4*>(S1 + sb + (k0));                 \
-    g2a = *reinterpret_cast<const uint4*>(S2 + sa + (k0));                 \
-    g2b = *reinterpret_cast<const uint4*>(S2 + sb + (k0));                 \
-    goa = *reinterpret_cast<const uint4*>(O + oa + (k0));                  \
-    gob = *reinterpret_cast<const uint4*>(O + ob + (k0));
-#define AFMM_LSTORE(dst)                                                   \
-    *reinterpret_cast<uint4*>((dst) + 0 * kPlane + la) = g0a;              \
-    *reinterpret_cast<uint4*>((dst) + 0 * kPlane + lb) = g0b;              \
-    *reinterpret_cast<uint4*>((dst) + 1 * kPlane + la) = g1a;              \
-    *reinterpret_cast<uint4*>((dst) + 1 * kPlane + lb) = g1b;              \
-    *reinterpret_cast<uint4*>((dst) + 2 * kPlane + la) = g2a;              \
-    *reinterpret_cast<uint4*>((dst) + 2 * kPlane + lb) = g2b;              \
-    *reinterpret_cast<uint4*>((dst) + 3 * kPlane + la) = goa;              \
-    *reinterpret_cast<uint4*>((dst) + 3 * kPlane + lb) = gob;
-
-    f32x16 acc_hi[2][2], acc_lo[2][2];
+    f32x16 acc_hi[4], acc_lo[4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                acc_hi[i][j][v] = 0.0f;
-                acc_lo[i][j][v] = 0.0f;
-            }
+        for (int v = 0; v < 16; ++v) {
+            acc_hi[i][v] = 0.0f;
+            acc_lo[i][v] = 0.0f;
+        }
 
+    // Fragment rows are a multiple of 32 plus fr, and swz(32 a + fr) == swz(fr):
+    // one swizzled chunk offset per lane and K step.
+    const int fr = lane & 31, fq = lane >> 5;
+    const int fo0 = fr * kGK + ((fq ^ swz(fr)) * 8);        // K step 0: chunks 0, 1
+    const int fo1 = fr * kGK + (((fq + 2) ^ swz(fr)) * 8);  // K step 1: chunks 2, 3
+#define AFMM_FRAG(cur, off) (*reinterpret_cast<const bf16x8*>((cur) + (off)))
+#define AFMM_MFMA(acc, a, b) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    // Both 16-wide K steps of the stage in buffer cur: hi into its own set,
+    // lo then mid into the second.
+#define AFMM_COMPUTE(cur)                                                                 \
+    _Pragma("unroll") for (int kk = 0; kk < 2; ++kk) {                                    \
+        const int fo = kk ? fo1 : fo0;                                                    \
+        bf16x8 fi[4], fs[3];                                                              \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                     \
+            fi[i] = AFMM_FRAG(cur, (wi + 32 * i) * kGK + fo);                             \
+        _Pragma("unroll") for (int t = 0; t < 3; ++t)                                     \
+            fs[t] = AFMM_FRAG(cur, kPlaneI + t * kPlaneS + wsr * kGK + fo);               \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
+            if (CASE_A) { AFMM_MFMA(acc_hi[i], fs[0], fi[i]) } else { AFMM_MFMA(acc_hi[i], fi[i], fs[0]) } \
+        }                                                                                 \
+        _Pragma("unroll") for (int t = 2; t >= 1; --t)                                    \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
+            if (CASE_A) { AFMM_MFMA(acc_lo[i], fs[t], fi[i]) } else { AFMM_MFMA(acc_lo[i], fi[i], fs[t]) } \
+        }                                                                                 \
+    }
+
+    // Global loads run two stages ahead of the MFMAs through two register
+    // sets: stage s + 2 is loaded into one set while stage s is computed, and
+    // the other set (stage s + 1) is written to the free LDS buffer at the end
+    // of stage s.  ld is a multiple of 64, so the stage count is even and the
+    // loop takes stages in pairs (s in buffer 0, s + 1 in buffer 1).
     const int n_k = (int)(ld / kGK);
-    AFMM_GLOAD(0)
-    AFMM_LSTORE(lds)
+    uint4 ga0, ga1, ga2, ga3, ga4, ga5, ga6, gb0, gb1, gb2, gb3, gb4, gb5, gb6;
+    uint16_t* const buf0 = lds;
+    uint16_t* const buf1 = lds + kStage;
+    AFMM_GLOAD(ga, 0)
+    AFMM_GLOAD(gb, kGK)
+    AFMM_LSTORE(buf0, ga)
     __syncthreads();
-    const int fr = lane & 31, fk = (lane >> 5) * 8;
-    // fragment rows inside the stage: A rows (wm + 32 i + fr), B rows (wc + 32 j + fr)
-    const int ra0 = (wm + fr) * kLdsRow + fk, ra1 = ra0 + 32 * kLdsRow;
-    const int rb0 = (wc + fr) * kLdsRow + fk, rb1 = rb0 + 32 * kLdsRow;
-    // plane of the A operand for term s, and of the B operand
-    constexpr int PA0 = TRIPLE_A ? 0 : 3, PA1 = TRIPLE_A ? 1 : 3, PA2 = TRIPLE_A ? 2 : 3;
-    constexpr int PB0 = TRIPLE_A ? 3 : 0, PB1 = TRIPLE_A ? 3 : 1, PB2 = TRIPLE_A ? 3 : 2;
-    for (int ks = 0; ks < n_k; ++ks) {
-        const uint16_t* cur = lds + (ks & 1) * STAGE;
-        const bool more = ks + 1 < n_k;
-        if (more) {
-            AFMM_GLOAD((ks + 1) * kGK)
+    for (int ks = 0; ks < n_k; ks += 2) {
+        if (ks + 2 < n_k) {
+            AFMM_GLOAD(ga, (int64_t)(ks + 2) * kGK)
         }
-#pragma unroll
-        for (int kk = 0; kk < kGK; kk += 16) {
-#define AFMM_FRAG(plane, off) (*reinterpret_cast<const bf16x8*>(cur + (plane) * kPlane + (off) + kk))
-            const bf16x8 a00 = AFMM_FRAG(PA0, ra0), a01 = AFMM_FRAG(PA0, ra1);
-            const bf16x8 b00 = AFMM_FRAG(PB0, rb0), b01 = AFMM_FRAG(PB0, rb1);
-            // term 0 (hi) into its own accumulators
-            acc_hi[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a00, b00, acc_hi[0][0], 0, 0, 0);
-            acc_hi[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a00, b01, acc_hi[0][1], 0, 0, 0);
-            acc_hi[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a01, b00, acc_hi[1][0], 0, 0, 0);
-            acc_hi[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a01, b01, acc_hi[1][1], 0, 0, 0);
-            // terms 2 (lo) then 1 (mid) into the second set
-            const bf16x8 a20 = AFMM_FRAG(PA2, ra0), a21 = AFMM_FRAG(PA2, ra1);
-            const bf16x8 b20 = AFMM_FRAG(PB2, rb0), b21 = AFMM_FRAG(PB2, rb1);
-            acc_lo[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a20, b20, acc_lo[0][0], 0, 0, 0);
-            acc_lo[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a20, b21, acc_lo[0][1], 0, 0, 0);
-            acc_lo[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a21, b20, acc_lo[1][0], 0, 0, 0);
-            acc_lo[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a21, b21, acc_lo[1][1], 0, 0, 0);
-            const bf16x8 a10 = AFMM_FRAG(PA1, ra0), a11 = AFMM_FRAG(PA1, ra1);
-            const bf16x8 b10 = AFMM_FRAG(PB1, rb0), b11 = AFMM_FRAG(PB1, rb1);
-            acc_lo[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a10, b10, acc_lo[0][0], 0, 0, 0);
-            acc_lo[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a10, b11, acc_lo[0][1], 0, 0, 0);
-            acc_lo[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a11, b10, acc_lo[1][0], 0, 0, 0);
-            acc_lo[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a11, b11, acc_lo[1][1], 0, 0, 0);
-#undef AFMM_FRAG
+        AFMM_COMPUTE(buf0)
+        AFMM_LSTORE(buf1, gb)
+        __syncthreads();
+        if (ks + 3 < n_k) {
+            AFMM_GLOAD(gb, (int64_t)(ks + 3) * kGK)
         }
-        if (more) {
-            uint16_t* nxt = lds + ((ks + 1) & 1) * STAGE;
-            AFMM_LSTORE(nxt)
+        AFMM_COMPUTE(buf1)
+        if (ks + 2 < n_k) {
+            AFMM_LSTORE(buf0, ga)
         }
         __syncthreads();
     }
+#undef AFMM_FRAG
+#undef AFMM_MFMA
+#undef AFMM_COMPUTE
+#undef AFMM_GLD
 #undef AFMM_GLOAD
+#undef AFMM_LST
 #undef AFMM_LSTORE
 
+    // block i covers I rows wi + 32 i .. +31 and S rows wsr .. wsr + 31; the
+    // MFMA's A operand (its result rows) is the I side for case B and the S
+    // side for case A.
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = m0 + wm + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v & 3);
-                const int col = c0 + wc + j * 32 + (lane & 31);
-                if (row < M && col < N) Z[(int64_t)row * ldz + col] = acc_hi[i][j][v] + acc_lo[i][j][v];
-            }
+        for (int v = 0; v < 16; ++v) {
+            const int a = 8 * (v / 4) + 4 * (lane >> 5) + (v & 3), b = lane & 31;
+            const int row = CASE_A ? s0 + wsr + a : i0 + wi + 32 * i + a;
+            const int col = CASE_A ? i0 + wi + 32 * i + b : s0 + wsr + b;
+            if (row < M && col < N) Z[(int64_t)row * ldz + col] = acc_hi[i][v] + acc_lo[i][v];
+        }
 }
 
-hipError_t launch_gemm_bf16x3(int M, int N, const uint16_t* A0, const uint16_t* A1,
-                              const uint16_t* A2, const uint16_t* B0, const uint16_t* B1,
-                              const uint16_t* B2, int64_t ld, float* Z, int64_t ldz,
-                              hipStream_t s) {
-    // A planes: split_rows_pad(M) rows, B planes: split_rows_pad(N) rows, K pitch ld
-    const int tiles_m = (M + kGM - 1) / kGM, tiles_n = (N + kGN - 1) / kGN;
-    const int n_tiles = tiles_m * tiles_n;
-    const bool triple_a = A0 != A1;
-    if (triple_a)
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(256), 0, s, M, N, A0, A1,
-                           A2, B0, B1, B2, ld, Z, ldz, tiles_m, tiles_n);
+hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, const uint16_t* S0,
+                              const uint16_t* S1, const uint16_t* S2, int64_t ld, float* Z,
+                              int64_t ldz, hipStream_t s) {
+    // I plane: split_int_rows_pad(rows) rows, S planes: split_real_rows_pad(rows)
+    // rows, K pitch ld (a multiple of 64)
+    const int rows_i = case_a ? N : M, rows_s = case_a ? M : N;
+    const int tiles_i = (rows_i + kTI - 1) / kTI, tiles_s = (rows_s + kTS - 1) / kTS;
+    const int n_tiles = tiles_i * tiles_s;
+    if (case_a)
+        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(256), 0, s, M, N, I, S0,
+                           S1, S2, ld, Z, ldz, tiles_i, tiles_s);
     else
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(256), 0, s, M, N, A0,
-                           A1, A2, B0, B1, B2, ld, Z, ldz, tiles_m, tiles_n);
+        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(256), 0, s, M, N, I, S0,
+                           S1, S2, ld, Z, ldz, tiles_i, tiles_s);
     return hipGetLastError();
 }
 
