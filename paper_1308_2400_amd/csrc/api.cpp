@@ -332,21 +332,28 @@ afmm_status split_run(afmm_case c, const Shape& p, const void* X, const void* Y,
     uint16_t* P[4];
     for (int q = 0; q < 4; ++q) P[q] = reinterpret_cast<uint16_t*>(sc.at(L.planes[q]));
     const int m = (int)p.m, k = (int)p.k, n = (int)p.n;
-    if (c == AFMM_CASE_A) {
-        // A operand: X's three terms [i][k]; B operand: Y as bf16 turned to [j][k]
-        AFMM_HIP(launch_split_real(static_cast<const float*>(X), m, k, p.ldx, false, P[0], P[1],
-                                   P[2], L.ld, L.rows_real, s));
-        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(Y), k, n, p.ldy, true, P[3], L.ld,
-                                    L.rows_int, s));
-        AFMM_HIP(launch_gemm_bf16x3(c == AFMM_CASE_A, m, n, P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
-    } else {
-        // A operand: X as bf16 [i][k]; B operand: Y's three terms turned to [j][k]
-        AFMM_HIP(launch_int_to_bf16(static_cast<const int32_t*>(X), m, k, p.ldx, false, P[3], L.ld,
-                                    L.rows_int, s));
-        AFMM_HIP(launch_split_real(static_cast<const float*>(Y), k, n, p.ldy, true, P[0], P[1],
-                                   P[2], L.ld, L.rows_real, s));
-        AFMM_HIP(launch_gemm_bf16x3(c == AFMM_CASE_A, m, n, P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
-    }
+    // case A: X's three terms [i][k], Y as bf16 turned to [j][k];
+    // case B: X as bf16 [i][k], Y's three terms turned to [j][k]
+    const bool case_a = c == AFMM_CASE_A;
+    SplitPrepArgs a;
+    a.I = static_cast<const int32_t*>(case_a ? Y : X);
+    a.i_rows = case_a ? k : m;
+    a.i_cols = case_a ? n : k;
+    a.ldi = case_a ? p.ldy : p.ldx;
+    a.ip = P[3];
+    a.i_tiles_o = L.rows_int / 64;
+    a.R = static_cast<const float*>(case_a ? X : Y);
+    a.r_rows = case_a ? m : k;
+    a.r_cols = case_a ? k : n;
+    a.ldr = case_a ? p.ldx : p.ldy;
+    a.hi = P[0];
+    a.mid = P[1];
+    a.lo = P[2];
+    a.r_tiles_o = L.rows_real / 64;
+    a.ld = L.ld;
+    a.int_blocks = (int)((int64_t)a.i_tiles_o * (L.ld / 64));
+    AFMM_HIP(launch_split_prep(case_a, a, s));
+    AFMM_HIP(launch_gemm_bf16x3(case_a, m, n, P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
     return AFMM_OK;
 }
 

@@ -105,13 +105,25 @@ struct BaseUniformArgs {
 hipError_t launch_base_uniform(const BaseUniformArgs& a, int R, int C, int W, hipStream_t s);
 bool base_uniform_supported(int R, int C, int W);
 
-// split.hip.  R / I: rows x cols with leading dimension ldr / ldi; planes
-// [rows_pad x ld] bfloat16, K-contiguous.
-hipError_t launch_split_real(const float* R, int rows, int cols, int64_t ldr, bool transpose,
-                             uint16_t* hi, uint16_t* mid, uint16_t* lo, int64_t ld, int rows_pad,
-                             hipStream_t s);
-hipError_t launch_int_to_bf16(const int32_t* I, int rows, int cols, int64_t ldi, bool transpose,
-                              uint16_t* out, int64_t ld, int rows_pad, hipStream_t s);
+// split.hip.  The integer factor I (i_rows x i_cols, pitch ldi) becomes the
+// bfloat16 plane ip, the real factor R (r_rows x r_cols, pitch ldr) the term
+// planes hi, mid, lo; planes are [64 * tiles_o x ld] bfloat16, K-contiguous,
+// zero outside the factor.  int_blocks = i_tiles_o * (ld / 64).
+struct SplitPrepArgs {
+    const int32_t* I;
+    int i_rows, i_cols;
+    int64_t ldi;
+    uint16_t* ip;
+    int i_tiles_o;
+    const float* R;
+    int r_rows, r_cols;
+    int64_t ldr;
+    uint16_t *hi, *mid, *lo;
+    int r_tiles_o;
+    int64_t ld;
+    int int_blocks;
+};
+hipError_t launch_split_prep(bool case_a, const SplitPrepArgs& a, hipStream_t s);
 // Z (M x N, pitch ldz) from the integer plane I and the term planes S0..S2
 // (hi, mid, lo), all with K pitch ld; I has one row per column of Z in case A
 // and per row of Z in case B, the term planes the other.

@@ -60,13 +60,11 @@ __device__ __forceinline__ void load_block(const T* __restrict__ in, int rows, i
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict__ in, int rows,
-                                                        int cols, int64_t ldi,
-                                                        uint16_t* __restrict__ hi,
-                                                        uint16_t* __restrict__ mid,
-                                                        uint16_t* __restrict__ lo, int64_t ld) {
-    __shared__ float tile[64][65];
-    const int o0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+__device__ __forceinline__ void split_real_block(const float* __restrict__ in, int rows, int cols,
+                                                 int64_t ldi, uint16_t* __restrict__ hi,
+                                                 uint16_t* __restrict__ mid,
+                                                 uint16_t* __restrict__ lo, int64_t ld, int o0,
+                                                 int c0, float (*tile)[65]) {
     load_block<TRANS>(in, rows, cols, ldi, o0, c0, tile);
     __syncthreads();
     for (int h = 0; h < 2; ++h) {
@@ -92,11 +90,9 @@ __global__ __launch_bounds__(256) void split_real_kernel(const float* __restrict
 }
 
 template <bool TRANS>
-__global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict__ in, int rows,
-                                                      int cols, int64_t ldi,
-                                                      uint16_t* __restrict__ out, int64_t ld) {
-    __shared__ int32_t tile[64][65];
-    const int o0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+__device__ __forceinline__ void int_bf16_block(const int32_t* __restrict__ in, int rows, int cols,
+                                               int64_t ldi, uint16_t* __restrict__ out, int64_t ld,
+                                               int o0, int c0, int32_t (*tile)[65]) {
     load_block<TRANS>(in, rows, cols, ldi, o0, c0, tile);
     __syncthreads();
     for (int h = 0; h < 2; ++h) {
@@ -115,28 +111,35 @@ __global__ __launch_bounds__(256) void int_bf16_kernel(const int32_t* __restrict
     }
 }
 
-hipError_t launch_split_real(const float* R, int rows, int cols, int64_t ldr, bool transpose,
-                             uint16_t* hi, uint16_t* mid, uint16_t* lo, int64_t ld, int rows_pad,
-                             hipStream_t s) {
-    dim3 grid(rows_pad / 64, (unsigned)(ld / 64));
-    if (transpose)
-        hipLaunchKernelGGL(split_real_kernel<true>, grid, dim3(256), 0, s, R, rows, cols, ldr, hi,
-                           mid, lo, ld);
-    else
-        hipLaunchKernelGGL(split_real_kernel<false>, grid, dim3(256), 0, s, R, rows, cols, ldr, hi,
-                           mid, lo, ld);
-    return hipGetLastError();
+// Both conversions in one launch: blocks [0, int_blocks) fill the integer
+// plane, the rest the three term planes; block b of a plane with tiles_o
+// 64-row output blocks covers output rows 64 (b % tiles_o) and K columns
+// 64 (b / tiles_o).  The integer factor is the one turned round in case A
+// (Y[k][j] -> [j][k]), the real factor in case B (Y[k][j] -> [j][k]).
+template <bool CASE_A>
+__global__ __launch_bounds__(256) void split_prep_kernel(SplitPrepArgs a) {
+    __shared__ uint32_t tile[64][65];
+    int b = blockIdx.x;
+    if (b < a.int_blocks) {
+        int_bf16_block<CASE_A>(a.I, a.i_rows, a.i_cols, a.ldi, a.ip, a.ld, (b % a.i_tiles_o) * 64,
+                               (b / a.i_tiles_o) * 64, reinterpret_cast<int32_t(*)[65]>(tile));
+    } else {
+        b -= a.int_blocks;
+        split_real_block<!CASE_A>(a.R, a.r_rows, a.r_cols, a.ldr, a.hi, a.mid, a.lo, a.ld,
+                                  (b % a.r_tiles_o) * 64, (b / a.r_tiles_o) * 64,
+                                  reinterpret_cast<float(*)[65]>(tile));
+    }
 }
 
-hipError_t launch_int_to_bf16(const int32_t* I, int rows, int cols, int64_t ldi, bool transpose,
-                              uint16_t* out, int64_t ld, int rows_pad, hipStream_t s) {
-    dim3 grid(rows_pad / 64, (unsigned)(ld / 64));
-    if (transpose)
-        hipLaunchKernelGGL(int_bf16_kernel<true>, grid, dim3(256), 0, s, I, rows, cols, ldi, out,
-                           ld);
+hipError_t launch_split_prep(bool case_a, const SplitPrepArgs& a, hipStream_t s) {
+    const int64_t k_tiles = a.ld / 64;
+    const int64_t blocks = (int64_t)(a.int_blocks + a.r_tiles_o * k_tiles);
+    if (a.int_blocks != (int64_t)a.i_tiles_o * k_tiles || blocks > INT32_MAX)
+        return hipErrorInvalidValue;
+    if (case_a)
+        hipLaunchKernelGGL(split_prep_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(int_bf16_kernel<false>, grid, dim3(256), 0, s, I, rows, cols, ldi, out,
-                           ld);
+        hipLaunchKernelGGL(split_prep_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -120,7 +120,8 @@ def test_rect_last_row_ends_the_allocation(dev, case):
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
-@pytest.mark.parametrize("shape", [(1, 1, 1), (200, 57, 333), (513, 1024, 70), (96, 2000, 300)],
+@pytest.mark.parametrize("shape", [(1, 1, 1), (200, 57, 333), (513, 1024, 70), (96, 2000, 300),
+                                   (257, 70, 65), (65, 70, 257), (600, 130, 129)],
                          ids=str)
 def test_rect_split_error(dev, case, shape):
     import torch

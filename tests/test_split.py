@@ -36,7 +36,8 @@ def _rand_case(case, n, seed, int_hi=9, dens=0.6):
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
-@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 127, 128, 129, 300, 517])
+# edges of the GEMM's block tile: 64 rows of the term planes, 256 of the integer plane
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257, 300, 517])
 def test_split_small_sizes(dev, case, n):
     X, Y = _rand_case(case, n, 200 + n)
     Z = _split(dev, case, X, Y)
