@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "split.hpp"
 #include "strict_acc.hpp"
 #include "strict_rows.hpp"
 

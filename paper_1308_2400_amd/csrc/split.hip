@@ -17,7 +17,7 @@
 // Operand layout: every plane is K-contiguous with one row per row of Z (the
 // factor on the left) or per column of Z (the factor on the right), zero padded
 // to the block tile so the GEMM has no bounds checks inside the K loop.
-#include "common.hpp"
+#include "split.hpp"
 
 namespace afmm {
 
