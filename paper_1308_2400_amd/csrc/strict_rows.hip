@@ -128,40 +128,62 @@ __global__ __launch_bounds__(W * kWave) void rep_rows_kernel(
         const uint2* __restrict__ yb = yent + (int64_t)band * kd * T::CT;
         const int32_t* __restrict__ yl = ylen + (int64_t)band * kd;
         for (int xc = 0; xc < nx; xc += kWave) {
-            // 64 of row i's entries, one per lane; taken one at a time below
-            const uint2 xe = xc + lane < nx ? xl[xc + lane] : make_uint2(0u, 0u);
+            // 64 of row i's entries, one per lane, taken one at a time below;
+            // each lane also fetches the length of its entry's Y list
+            const bool xin = xc + lane < nx;
+            const uint2 xe = xin ? xl[xc + lane] : make_uint2(0u, 0u);
+            const int lenv = xin ? yl[(int)xe.y] : 0;
             const int cnt = min(kWave, nx - xc);
-            // entry 0's list: its length and first 64 entries, fetched ahead
-            int k = __builtin_amdgcn_readlane((int)xe.y, 0);
-            int len = yl[k];
-            uint2 ye = yb[(int64_t)k * T::CT + lane];
-            for (int e = 0; e < cnt; ++e) {
-                const uint32_t xv = (uint32_t)__builtin_amdgcn_readlane((int)xe.x, e);
-                const int k_cur = k, len_cur = len;
-                const uint2 ye_cur = ye;
-                if (e + 1 < cnt) {  // the next entry's list goes out before this one's work
-                    k = __builtin_amdgcn_readlane((int)xe.y, e + 1);
-                    len = yl[k];
-                    ye = yb[(int64_t)k * T::CT + lane];
-                }
-                for (int yc = 0; yc < len_cur; yc += kWave) {
-                    const uint2 y = yc == 0 ? ye_cur : yb[(int64_t)k_cur * T::CT + yc + lane];
-                    if (lane < len_cur - yc) {
-                        const int j = (int)y.y;
-                        float z = zrow[j];
-                        if (CASE_A) {
-                            // base X[i,k] for the wave, count Y[k,j] for the lane
-                            const float base = __uint_as_float(xv);
-                            for (int32_t r = (int32_t)y.x; r > 0; --r) z = z + base;
-                        } else {
-                            // count X[i,k] for the wave, base Y[k,j] for the lane
-                            const float base = __uint_as_float(y.x);
-                            for (int32_t r = (int32_t)xv; r > 0; --r) z = z + base;
-                        }
-                        zrow[j] = z;
-                    }
-                }
+            // The first 64 entries of entry e's Y list are requested while
+            // the three entries before it are processed: the loop takes
+            // entries four at a time, each with a register of its own that is
+            // refilled for entry e + 4 as soon as entry e is done, so no load
+            // result is moved while in flight.  The requests are unconditional
+            // (an index past the last entry reads the last entry's list again)
+            // so the wait counts stay exact.
+#define AFMM_YFETCH(e)                                                                    \
+    yb[(int64_t)__builtin_amdgcn_readlane((int)xe.y, min((e), cnt - 1)) * T::CT + lane]
+#define AFMM_ADD(yv)                                                                      \
+    {                                                                                     \
+        const int j = (int)(yv).y;                                                         \
+        float z = zrow[j];                                                                \
+        if (CASE_A) {                                                                     \
+            /* base X[i,k] for the wave, count Y[k,j] for the lane */                     \
+            const float base = __uint_as_float(xv);                                       \
+            for (int32_t r = (int32_t)(yv).x; r > 0; --r) z = z + base;                    \
+        } else {                                                                          \
+            /* count X[i,k] for the wave, base Y[k,j] for the lane */                     \
+            const float base = __uint_as_float((yv).x);                                    \
+            for (int32_t r = (int32_t)xv; r > 0; --r) z = z + base;                       \
+        }                                                                                 \
+        zrow[j] = z;                                                                      \
+    }
+#define AFMM_ENTRY(e, yreg)                                                               \
+    {                                                                                     \
+        if ((e) < cnt) {                                                                  \
+            const uint32_t xv = (uint32_t)__builtin_amdgcn_readlane((int)xe.x, (e));      \
+            const int len_cur = __builtin_amdgcn_readlane(lenv, (e));                     \
+            if (lane < len_cur) AFMM_ADD(yreg)                                            \
+            if (len_cur > kWave) {                                                        \
+                const int k_cur = __builtin_amdgcn_readlane((int)xe.y, (e));              \
+                for (int yc = kWave; yc < len_cur; yc += kWave) {                         \
+                    const uint2 y = yb[(int64_t)k_cur * T::CT + yc + lane];               \
+                    if (lane < len_cur - yc) AFMM_ADD(y)                                  \
+                }                                                                         \
+            }                                                                             \
+        }                                                                                 \
+        yreg = AFMM_YFETCH((e) + 4);                                                      \
+    }
+            uint2 y0 = AFMM_YFETCH(0), y1 = AFMM_YFETCH(1), y2 = AFMM_YFETCH(2), y3 = AFMM_YFETCH(3);
+            for (int e = 0; e < cnt; e += 4) {
+                AFMM_ENTRY(e, y0)
+                AFMM_ENTRY(e + 1, y1)
+                AFMM_ENTRY(e + 2, y2)
+                AFMM_ENTRY(e + 3, y3)
             }
+#undef AFMM_ENTRY
+#undef AFMM_ADD
+#undef AFMM_YFETCH
         }
     }
     __syncthreads();
