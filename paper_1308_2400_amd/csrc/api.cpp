@@ -515,9 +515,10 @@ afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void* X, const voi
     const double d_real = (double)h[0] / nn, d_int = (double)h[1] / nn;
     // thresholds from measurements on MI355X (n = 2048..16384): the row-list form
     // while a row meets few non-zero pairs per k (d_real * d_int * n, its work per
-    // k of a row, is at most 24), the compacted-base form when the real factor
-    // alone is very sparse, the size-keyed choice otherwise
-    if (d_real * d_int * (double)n <= 24.0)
+    // k of a row, is at most 32 in case A, where a lane loops its own count, and
+    // 42 in case B), the compacted-base form when the real factor alone is very
+    // sparse, the size-keyed choice otherwise
+    if (d_real * d_int * (double)n <= (c == AFMM_CASE_A ? 32.0 : 42.0))
         *out = afmm_config{7, 1, n <= 2896 ? 16 : 32, 16, 1, 16};
     else if (d_real <= 0.06)
         *out = n <= 2896 ? afmm_config{4, 1, 64, 8, 2, 8} : afmm_config{4, 2, 32, 8, 2, 8};

@@ -59,17 +59,27 @@ __global__ __launch_bounds__(256) void compact_rows_kernel(const uint32_t* __res
     const int width = min(ct, cols - band * ct);
     uint2* __restrict__ out = ent + seg * ct;
     int count = 0;
-    for (int ch = 0; ch < width; ch += kWave) {
-        const int c = ch + lane;
-        const uint32_t v = c < width ? src[c] : 0u;
-        const bool take = c < width && (INT ? (int32_t)v > 0 : __uint_as_float(v) != 0.0f);
-        const uint64_t mk = __ballot(take);
-        if (take) {
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
-            out[count + (int)below] = make_uint2(v, (uint32_t)c);
+    // four chunks of 64 columns per step: their loads go out together, then
+    // the chunks are ranked in column order
+    for (int ch = 0; ch < width; ch += 4 * kWave) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = ch + u * kWave + lane;
+            v[u] = c < width ? src[c] : 0u;
         }
-        count += __popcll(mk);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = ch + u * kWave + lane;
+            const bool take = c < width && (INT ? (int32_t)v[u] > 0 : __uint_as_float(v[u]) != 0.0f);
+            const uint64_t mk = __ballot(take);
+            if (take) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                out[count + (int)below] = make_uint2(v[u], (uint32_t)c);
+            }
+            count += __popcll(mk);
+        }
     }
     if (lane == 0) lens[seg] = count;
 }

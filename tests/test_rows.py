@@ -105,14 +105,17 @@ def test_rows_quadratic_regime_sampled(dev, case):
 
 @pytest.mark.parametrize("case", ["A", "B"])
 def test_suggested_configuration(dev, case):
-    """afmm_suggest_config: row lists when d_real * d_int * n <= 24, compacted bases
-    when only the real factor is very sparse (<= 6 %), the size-keyed choice
-    otherwise and below n = 1024; the suggested configuration gives the default's
-    bits."""
+    """afmm_suggest_config: row lists when d_real * d_int * n <= 32 (case A) or 42
+    (case B), compacted bases when only the real factor is very sparse (<= 6 %),
+    the size-keyed choice otherwise and below n = 1024; the suggested
+    configuration gives the default's bits.  (Positive counts are 6/7 of the
+    integer mask here.)"""
     afmm = _afmm()
     n = 2048
     for d_real, d_int, mapping in ((0.1, 0.1, 7), (0.05, 0.7, 4), (0.1, 0.5, None),
-                                   (0.9, 0.3, None)):
+                                   (0.9, 0.3, None),
+                                   # d_real * d_int * n = 37: row lists in case B only
+                                   (0.12, 0.175, 7 if case == "B" else None)):
         X, Y = _inputs(case, n, 40 + int(100 * d_real), d_real, d_int)
         Xd, Yd = _to(dev, X), _to(dev, Y)
         cfg = afmm.suggest_config(case, Xd, Yd)
