@@ -112,21 +112,22 @@ __device__ __forceinline__ void int_bf16_block(const int32_t* __restrict__ in, i
 }
 
 // Both conversions in one launch: blocks [0, int_blocks) fill the integer
-// plane, the rest the three term planes; block b of a plane with tiles_o
-// 64-row output blocks covers output rows 64 (b % tiles_o) and K columns
-// 64 (b / tiles_o).  The integer factor is the one turned round in case A
+// plane, the rest the three term planes; block b of a plane covers K columns
+// 64 (b % (ld / 64)) and output rows 64 (b / (ld / 64)), so blocks running
+// together write whole output rows.  The integer factor is the one turned round in case A
 // (Y[k][j] -> [j][k]), the real factor in case B (Y[k][j] -> [j][k]).
 template <bool CASE_A>
 __global__ __launch_bounds__(256) void split_prep_kernel(SplitPrepArgs a) {
     __shared__ uint32_t tile[64][65];
+    const int k_tiles = (int)(a.ld / 64);
     int b = blockIdx.x;
     if (b < a.int_blocks) {
-        int_bf16_block<CASE_A>(a.I, a.i_rows, a.i_cols, a.ldi, a.ip, a.ld, (b % a.i_tiles_o) * 64,
-                               (b / a.i_tiles_o) * 64, reinterpret_cast<int32_t(*)[65]>(tile));
+        int_bf16_block<CASE_A>(a.I, a.i_rows, a.i_cols, a.ldi, a.ip, a.ld, (b / k_tiles) * 64,
+                               (b % k_tiles) * 64, reinterpret_cast<int32_t(*)[65]>(tile));
     } else {
         b -= a.int_blocks;
         split_real_block<!CASE_A>(a.R, a.r_rows, a.r_cols, a.ldr, a.hi, a.mid, a.lo, a.ld,
-                                  (b % a.r_tiles_o) * 64, (b / a.r_tiles_o) * 64,
+                                  (b / k_tiles) * 64, (b % k_tiles) * 64,
                                   reinterpret_cast<float(*)[65]>(tile));
     }
 }
