@@ -157,15 +157,16 @@ __global__ __launch_bounds__(W * kWave) void rep_rows_kernel(
     {                                                                                     \
         const int j = (int)(yv).y;                                                         \
         float z = zrow[j];                                                                \
-        if (CASE_A) {                                                                     \
-            /* base X[i,k] for the wave, count Y[k,j] for the lane */                     \
-            const float base = __uint_as_float(xv);                                       \
-            for (int32_t r = (int32_t)(yv).x; r > 0; --r) z = z + base;                    \
-        } else {                                                                          \
-            /* count X[i,k] for the wave, base Y[k,j] for the lane */                     \
-            const float base = __uint_as_float((yv).x);                                    \
-            for (int32_t r = (int32_t)xv; r > 0; --r) z = z + base;                       \
+        /* CASE_A: base X[i,k] for the wave, count Y[k,j] for the lane; else   */    \
+        /* count X[i,k] for the wave, base Y[k,j] for the lane.  Two additions */    \
+        /* per trip, the same sequence of additions.                           */    \
+        const float base = __uint_as_float(CASE_A ? xv : (yv).x);                         \
+        int32_t r = (int32_t)(CASE_A ? (yv).x : xv);                                      \
+        for (; r >= 2; r -= 2) {                                                          \
+            z = z + base;                                                                 \
+            z = z + base;                                                                 \
         }                                                                                 \
+        if (r > 0) z = z + base;                                                          \
         zrow[j] = z;                                                                      \
     }
 #define AFMM_ENTRY(e, yreg)                                                               \
