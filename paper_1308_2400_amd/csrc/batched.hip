@@ -317,7 +317,7 @@ __device__ __forceinline__ void run_tile(const BatchProblem& b, int r0, int c0, 
     const int64_t p_sr = TRANS ? 1 : n, p_sk = TRANS ? n : 1;
     const int64_t z_sr = TRANS ? 1 : n, z_sc = TRANS ? n : 1;
     if constexpr (KP > 0)
-        rep_sparse_tile<R, C, kBW, KP, TRANS, ESC, 1>(n, n, n, b.P8, b.ldp, P32, p_sr, p_sk, b.Q,
+        rep_sparse_tile<R, C, kBW, KP, TRANS, ESC, 2>(n, n, n, b.P8, b.ldp, P32, p_sr, p_sk, b.Q,
                                                       b.ldq, b.Z, z_sr, z_sc, r0, c0, lds);
     else
         rep_uniform_tile<R, C, kBW, kBKP, true, TRANS, ESC>(n, n, n, b.P8, b.ldp, P32, p_sr, p_sk,
