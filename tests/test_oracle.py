@@ -73,6 +73,27 @@ def test_golden_bf16_rne():
         assert int(h) == int(c["bf16"], 16), c
 
 
+def _bf16_exact(h):
+    """bfloat16 pattern -> exact rational (normal and zero patterns only)."""
+    h = int(h)
+    sign = -1 if h & 0x8000 else 1
+    e, m = (h >> 7) & 0xFF, h & 0x7F
+    assert e != 0xFF
+    if e == 0:
+        return Fraction(sign * m, 2 ** 133)
+    return sign * Fraction(128 + m, 128) * Fraction(2) ** (e - 127)
+
+
+@pytest.mark.parametrize("c", _load("split_bf16x3.json")["cases"], ids=lambda c: c["x"])
+def test_golden_split_bf16x3(c):
+    """hi, mid and lo of hand-worked values where the rounding of mid decides the
+    patterns (a truncated or round-half-away mid fails), and hi + mid + lo == x."""
+    x = _hex_f32(c["x"])
+    hi, mid, lo = (int(t[0]) for t in oracle.split_bf16x3(np.array([x], np.float32)))
+    assert (hi, mid, lo) == (int(c["hi"], 16), int(c["mid"], 16), int(c["lo"], 16)), c["why"]
+    assert _bf16_exact(hi) + _bf16_exact(mid) + _bf16_exact(lo) == Fraction(float(x))
+
+
 # --------------------------------------------------------------------------
 # Brute force against exact rationals (n <= 8)
 
