@@ -151,6 +151,23 @@ afmm_status afmm_count_adds_ex(afmm_case c, int64_t m, int64_t k, int64_t n, con
                                size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * The split form's operand conversion, read back (for checking it against an
+ * independent split; not needed for computing products).  Runs the conversion
+ * pass a split-mode multiply runs on (X, Y) and writes, in device memory:
+ *   d_terms: three n x n bfloat16 bit patterns, hi then mid then lo, of the
+ *            real factor in its own row-major layout (X[i][k] in case A,
+ *            Y[k][j] in case B): hi = RNE_bf16(x), mid = RNE_bf16(x - hi),
+ *            lo = RNE_bf16(x - hi - mid);
+ *   d_ints:  the n x n integer factor as bfloat16 patterns, row-major in its
+ *            own layout (a count <= 0 becomes +0; 1..256 are exact).
+ * workspace: afmm_workspace_size(c, n, AFMM_MODE_SPLIT_BF16X3) bytes or NULL
+ * (stream-ordered allocation).  Asynchronous on `stream`.
+ */
+afmm_status afmm_split_terms(afmm_case c, int64_t n, const void *X, const void *Y,
+                             uint16_t *d_terms, uint16_t *d_ints, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Synchronous data check: runs the counting pass on `stream`, waits for it,
  * and returns AFMM_ERR_NEGATIVE_INT, AFMM_ERR_INT_RANGE (split mode, an
  * entry > 256), AFMM_ERR_COUNT_OVERFLOW or AFMM_OK.
@@ -254,16 +271,19 @@ afmm_status afmm_set_tuning(int32_t count, const int32_t *cases, const int64_t *
 
 /* ---------------------------------------------------------------------------
  * Batched products: many independent AFMM products of uneven size, density
- * and integer range in one persistent launch.  Work is cut into tiles and
- * handed out largest-first by each tile's addition count (the method's own
- * cost, Section 2.2), measured on the device from the data.
+ * and integer range.  In strict mode they run in one persistent launch: work
+ * is cut into tiles and handed out largest-first by each tile's cost, which is
+ * data-dependent as Section 2.2 says: the lane additions the kernel issues for
+ * the tile (the integer factor's counts summed over the tile's rows, times the
+ * tile's width) plus a per-(row, k) term, measured on the device from the data
+ * at every launch.
  */
 typedef struct {
     int32_t case_id; /* AFMM_CASE_A or AFMM_CASE_B                             */
     int32_t n;       /* 1 .. AFMM_MAX_BATCH_N                                  */
     const void *X;   /* case A: const float*, case B: const int32_t*           */
     const void *Y;   /* case A: const int32_t*, case B: const float*           */
-    float *Z;        /* output, must not overlap any X or Y of the batch       */
+    float *Z;        /* output, must not overlap any X, Y or other Z of the batch */
 } afmm_problem;
 
 #define AFMM_MAX_BATCH_N 8192
@@ -271,28 +291,36 @@ typedef struct {
 typedef struct afmm_plan afmm_plan;
 
 /*
- * Build a plan for `count` problems (host array, copied).  Strict mode only
- * (split mode returns AFMM_ERR_UNSUPPORTED).  Allocates the plan's device
- * tables and scratch on the current device.  The plan records the pointers;
- * the data they point to may change between launches.
+ * Build a plan for `count` (1 .. 4096) problems (host array, copied).
+ * Returns AFMM_ERR_ALIAS when some Z overlaps any X, Y or other Z of the
+ * batch (X and Y may be shared between problems).  Allocates the plan's
+ * device tables and scratch on the current device.  The plan records the
+ * pointers; the data they point to may change between launches.
+ * mode AFMM_MODE_STRICT: the persistent path above, bit-identical to single
+ * strict products.  mode AFMM_MODE_SPLIT_BF16X3: each product is the
+ * single-product split form (its conversion pass and matrix-core product,
+ * queued one after another), with the same result as afmm_multiply_caseA/B in
+ * split mode; the per-problem addition counts are still computed.
  */
-afmm_status afmm_plan_create(const afmm_problem *problems, int32_t count, afmm_mode mode,
-                             afmm_plan **out);
+afmm_status afmm_batched_plan_create(const afmm_problem *problems, int32_t count, afmm_mode mode,
+                                     afmm_plan **out);
 
 /*
- * Run the plan on `stream`: prepare operands, compute per-tile addition
- * counts, order the tiles largest-first, and run the persistent kernel.  The
- * first launch on a stream captures these steps into a HIP graph; later
- * launches replay it.  Launches of one plan must not overlap.
+ * Run the plan on `stream`: prepare operands, compute the per-problem addition
+ * counts and per-tile costs, order the tiles largest-first, and run the
+ * persistent kernel (split mode: the per-product conversions and products).
+ * The first launch captures these steps into a HIP graph; later launches
+ * replay it.  Launches of one plan must not overlap.
  */
-afmm_status afmm_plan_launch(afmm_plan *plan, hipStream_t stream);
+afmm_status afmm_batched_plan_launch(afmm_plan *plan, hipStream_t stream);
 
-/* Queue on `stream` a copy of the per-problem addition counts computed by
- * the plan's last launch into d_out (device, uint64[count]). */
-afmm_status afmm_plan_problem_adds(const afmm_plan *plan, uint64_t *d_out, hipStream_t stream);
+/* Queue on `stream` a copy of the per-problem addition counts (Section 2.2)
+ * computed by the plan's last launch into d_out (device, uint64[count]). */
+afmm_status afmm_batched_plan_problem_adds(const afmm_plan *plan, uint64_t *d_out,
+                                           hipStream_t stream);
 
 /* Release the plan (synchronises the device first). */
-afmm_status afmm_plan_destroy(afmm_plan *plan);
+afmm_status afmm_batched_plan_destroy(afmm_plan *plan);
 
 /* One-shot convenience: create, launch on `stream`, wait, destroy. */
 afmm_status afmm_multiply_batched(const afmm_problem *problems, int32_t count, afmm_mode mode,

@@ -107,6 +107,26 @@ def strict_f32(case, X, Y, rows=None, x_rows_only=False):
     return (caseA_f32 if case == "A" else caseB_f32)(X, Y, rows, x_rows_only)
 
 
+def strict_f32_threaded(case, X, Y, threads=None):
+    """The same strict loop over disjoint row ranges on several host threads (rows
+    of Z are independent, Section 2.1, so the result is bit-identical to one
+    call; the C loop runs outside the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    m = X.shape[0]
+    threads = max(1, min(threads or os.cpu_count() or 1, m))
+    bounds = np.linspace(0, m, threads + 1).astype(np.int64)
+    parts = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    X = np.ascontiguousarray(X)
+
+    def run(ab):
+        rows = np.arange(ab[0], ab[1], dtype=np.int64)
+        return strict_f32(case, X[ab[0]:ab[1]], Y, rows=rows, x_rows_only=True)
+
+    with ThreadPoolExecutor(len(parts)) as ex:
+        res = list(ex.map(run, parts))
+    return np.concatenate([z for z, _ in res]), sum(a for _, a in res)
+
+
 def product_f64(case, X, Y, rows=None, x_rows_only=False):
     """True product X.Y in binary64 (plain loop, k ascending) for the listed rows."""
     xdt, ydt = (np.float32, np.int32) if case == "A" else (np.int32, np.float32)

@@ -71,11 +71,12 @@ _SIGS = {
     "afmm_multiply_strict_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config), _vp,
                                      _sz, _vp], _ci),
     "afmm_set_tuning": ([_i32, _vp, _vp, _vp, _vp], _ci),
-    "afmm_plan_create": ([ctypes.POINTER(afmm_problem), _i32, _ci, ctypes.POINTER(_vp)], _ci),
-    "afmm_plan_launch": ([_vp, _vp], _ci),
-    "afmm_plan_problem_adds": ([_vp, _vp, _vp], _ci),
-    "afmm_plan_destroy": ([_vp], _ci),
+    "afmm_batched_plan_create": ([ctypes.POINTER(afmm_problem), _i32, _ci, ctypes.POINTER(_vp)], _ci),
+    "afmm_batched_plan_launch": ([_vp, _vp], _ci),
+    "afmm_batched_plan_problem_adds": ([_vp, _vp, _vp], _ci),
+    "afmm_batched_plan_destroy": ([_vp], _ci),
     "afmm_multiply_batched": ([ctypes.POINTER(afmm_problem), _i32, _ci, _vp], _ci),
+    "afmm_split_terms": ([_ci, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _ci),
     "afmm_status_string": ([_ci], ctypes.c_char_p),
     "afmm_last_hip_error": ([], _ci),
     "afmm_version": ([], ctypes.c_char_p),
@@ -307,7 +308,8 @@ def load_tuning(path=None):
 
 
 class Plan:
-    """A batch of independent products run by one persistent launch (strict mode)."""
+    """A batch of independent products: one persistent launch in strict mode, the
+    single-product split form per problem in split mode."""
 
     def __init__(self, problems, mode="strict"):
         """problems: list of (case, X, Y, Z) device tensors."""
@@ -318,23 +320,23 @@ class Plan:
             c, n = _operands(case, X, Y)
             arr[t] = afmm_problem(c, n, X.data_ptr(), Y.data_ptr(), Z.data_ptr())
         h = ctypes.c_void_p()
-        _check("plan_create", _lib.afmm_plan_create(arr, k, _mode_id(mode), ctypes.byref(h)))
+        _check("plan_create", _lib.afmm_batched_plan_create(arr, k, _mode_id(mode), ctypes.byref(h)))
         self._h = h
         self.count = k
 
     def launch(self):
-        _check("plan_launch", _lib.afmm_plan_launch(self._h, _stream()))
+        _check("plan_launch", _lib.afmm_batched_plan_launch(self._h, _stream()))
 
     def problem_adds(self):
         """Per-problem addition counts of the last launch (synchronises)."""
         torch = _torch()
         out = torch.empty(self.count, dtype=torch.int64, device="cuda")
-        _check("plan_problem_adds", _lib.afmm_plan_problem_adds(self._h, out.data_ptr(), _stream()))
+        _check("plan_problem_adds", _lib.afmm_batched_plan_problem_adds(self._h, out.data_ptr(), _stream()))
         return [int(v) & ((1 << 64) - 1) for v in out.cpu().tolist()]
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.afmm_plan_destroy(self._h)
+            _lib.afmm_batched_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -141,26 +141,6 @@ StrictLayout strict_layout(afmm_case c, const Shape& p, const afmm_config& cfg) 
     return L;
 }
 
-struct SplitLayout {
-    int rows_real, rows_int;  // padded rows of the real-term planes and the integer plane
-    int64_t ld;               // K pitch
-    size_t planes[4], total;  // three real-term planes, then the integer plane
-};
-
-// Split path: K-contiguous bfloat16 planes; the real factor's three terms
-// have one row per i (case A) or per j (case B), the integer plane the other.
-SplitLayout split_layout(afmm_case c, const Shape& p) {
-    SplitLayout L;
-    L.rows_real = split_real_rows_pad((int)(c == AFMM_CASE_A ? p.m : p.n));
-    L.rows_int = split_int_rows_pad((int)(c == AFMM_CASE_A ? p.n : p.m));
-    L.ld = round_up(p.k, 64);
-    Carve cv;
-    for (int q = 0; q < 3; ++q) L.planes[q] = cv.take((size_t)L.rows_real * L.ld * 2);
-    L.planes[3] = cv.take((size_t)L.rows_int * L.ld * 2);
-    L.total = cv.off;
-    return L;
-}
-
 // count scratch: per-k weights, per-row counts (when the caller passes none),
 // flags and total
 size_t count_ws(const Shape& p) {
@@ -324,37 +304,20 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
     return AFMM_OK;
 }
 
+SplitLayout split_layout(afmm_case c, const Shape& p) {
+    return split_planes_layout(c == AFMM_CASE_A, (int)p.m, (int)p.k, (int)p.n);
+}
+
 afmm_status split_run(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
                       void* ws, size_t ws_bytes, hipStream_t s) {
     const SplitLayout L = split_layout(c, p);
     Scratch sc;
     const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
     if (st != AFMM_OK) return st;
-    uint16_t* P[4];
-    for (int q = 0; q < 4; ++q) P[q] = reinterpret_cast<uint16_t*>(sc.at(L.planes[q]));
-    const int m = (int)p.m, k = (int)p.k, n = (int)p.n;
-    // case A: X's three terms [i][k], Y as bf16 turned to [j][k];
-    // case B: X as bf16 [i][k], Y's three terms turned to [j][k]
     const bool case_a = c == AFMM_CASE_A;
-    SplitPrepArgs a;
-    a.I = static_cast<const int32_t*>(case_a ? Y : X);
-    a.i_rows = case_a ? k : m;
-    a.i_cols = case_a ? n : k;
-    a.ldi = case_a ? p.ldy : p.ldx;
-    a.ip = P[3];
-    a.i_tiles_o = L.rows_int / 64;
-    a.R = static_cast<const float*>(case_a ? X : Y);
-    a.r_rows = case_a ? m : k;
-    a.r_cols = case_a ? k : n;
-    a.ldr = case_a ? p.ldx : p.ldy;
-    a.hi = P[0];
-    a.mid = P[1];
-    a.lo = P[2];
-    a.r_tiles_o = L.rows_real / 64;
-    a.ld = L.ld;
-    a.int_blocks = (int)((int64_t)a.i_tiles_o * (L.ld / 64));
-    AFMM_HIP(launch_split_prep(case_a, a, s));
-    AFMM_HIP(launch_gemm_bf16x3(case_a, m, n, P[3], P[0], P[1], P[2], L.ld, Z, p.ldz, s));
+    AFMM_HIP(launch_split_prepare(case_a, (int)p.m, (int)p.k, (int)p.n, X, p.ldx, Y, p.ldy, L,
+                                  sc.at(0), s));
+    AFMM_HIP(launch_split_gemm(case_a, (int)p.m, (int)p.n, L, sc.at(0), Z, p.ldz, s));
     return AFMM_OK;
 }
 
@@ -459,6 +422,32 @@ afmm_status afmm_count_adds_ex(afmm_case c, int64_t m, int64_t k, int64_t n, con
                                size_t workspace_bytes, hipStream_t stream) {
     return count_adds(c, Shape{m, k, n, ldx, ldy, n}, X, Y, d_total, d_row_counts, d_flags,
                       workspace, workspace_bytes, stream);
+}
+
+afmm_status afmm_split_terms(afmm_case c, int64_t n, const void* X, const void* Y,
+                             uint16_t* d_terms, uint16_t* d_ints, void* workspace,
+                             size_t workspace_bytes, hipStream_t stream) {
+    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !d_terms || !d_ints ||
+        (c != AFMM_CASE_A && c != AFMM_CASE_B))
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    const Shape p = square(n);
+    const SplitLayout L = split_layout(c, p);
+    Scratch sc;
+    if ((st = sc.get(workspace, workspace_bytes, L.total, stream)) != AFMM_OK) return st;
+    const bool case_a = c == AFMM_CASE_A;
+    AFMM_HIP(launch_split_prepare(case_a, (int)n, (int)n, (int)n, X, n, Y, n, L, sc.at(0),
+                                  stream));
+    const uint16_t* P[4];
+    for (int q = 0; q < 4; ++q) P[q] = reinterpret_cast<const uint16_t*>(sc.at(L.planes[q]));
+    // the real factor's planes are [i][k] in case A (its own orientation) and
+    // [j][k] in case B (turned); the integer plane the other way round
+    const size_t nn = (size_t)n * (size_t)n;
+    for (int q = 0; q < 3; ++q)
+        AFMM_HIP(launch_plane_unpack(P[q], L.ld, !case_a, (int)n, (int)n, d_terms + q * nn, stream));
+    AFMM_HIP(launch_plane_unpack(P[3], L.ld, case_a, (int)n, (int)n, d_ints, stream));
+    return AFMM_OK;
 }
 
 afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, afmm_mode mode,

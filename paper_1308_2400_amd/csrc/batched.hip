@@ -1,5 +1,7 @@
 // Batched persistent AFMM: many independent strict products of uneven size,
-// density and integer range in one persistent launch.
+// density and integer range in one persistent launch.  (Split-mode plans run
+// the counting kernels and then each product's split conversion and matrix-core
+// product; see afmm_batched_plan_create.)
 //
 // Per launch (captured once into a HIP graph, then replayed):
 //   1. reset      per-problem counters and the work-queue head
@@ -20,6 +22,7 @@
 
 #include "afmm.h"
 #include "sparse_body.hpp"
+#include "split.hpp"
 
 namespace afmm {
 namespace {
@@ -376,6 +379,11 @@ using namespace afmm;
 
 struct afmm_plan {
     int count = 0;
+    afmm_mode mode = AFMM_MODE_STRICT;
+    // split mode: each product's operands, plane layout and plane offset in mem
+    std::vector<afmm_problem> probs;
+    std::vector<SplitLayout> split_layouts;
+    std::vector<size_t> split_off;
     int device = 0;
     int64_t total_chunks = 0, total_rows = 0, total_tiles = 0;
     int persist_grid = 0;
@@ -397,14 +405,40 @@ afmm_status enqueue(afmm_plan* pl, hipStream_t s) {
     const int count = pl->count;
     hipLaunchKernelGGL(batch_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, count,
                        pl->d_adds, pl->d_isum, pl->d_esc, pl->d_head, pl->d_flags);
-    const int prep_grid = (int)std::min<int64_t>(pl->total_chunks, 65536);
-    hipLaunchKernelGGL(batch_prep_kernel, dim3(prep_grid), dim3(64, 4), 0, s, pl->d_probs, count,
-                       pl->total_chunks, pl->d_esc);
+    if (pl->mode == AFMM_MODE_STRICT) {
+        const int prep_grid = (int)std::min<int64_t>(pl->total_chunks, 65536);
+        hipLaunchKernelGGL(batch_prep_kernel, dim3(prep_grid), dim3(64, 4), 0, s, pl->d_probs,
+                           count, pl->total_chunks, pl->d_esc);
+    }
     const int row_blocks = (int)((pl->total_rows + 3) / 4);
     hipLaunchKernelGGL(batch_kstat_kernel, dim3(row_blocks), dim3(256), 0, s, pl->d_probs, count,
                        pl->total_rows, pl->d_wk, pl->d_isum, pl->d_flags);
     hipLaunchKernelGGL(batch_rows_kernel, dim3(row_blocks), dim3(256), 0, s, pl->d_probs, count,
                        pl->total_rows, pl->d_wk, pl->d_adds, pl->d_isum, pl->d_flags);
+    if (pl->mode == AFMM_MODE_SPLIT_BF16X3) {
+        // the counts above serve afmm_batched_plan_problem_adds; the products
+        // are the single-product split form, one conversion and one matrix-core
+        // launch each
+        uint8_t* m = static_cast<uint8_t*>(pl->mem);
+        for (int p = 0; p < count; ++p) {
+            const afmm_problem& q = pl->probs[p];
+            const bool case_a = q.case_id == AFMM_CASE_A;
+            const SplitLayout& L = pl->split_layouts[p];
+            uint8_t* base = m + pl->split_off[p];
+            hipError_t e = launch_split_prepare(case_a, q.n, q.n, q.n, q.X, q.n, q.Y, q.n, L, base, s);
+            if (e == hipSuccess) e = launch_split_gemm(case_a, q.n, q.n, L, base, q.Z, q.n, s);
+            if (e != hipSuccess) {
+                set_last_hip_error((int)e);
+                return AFMM_ERR_HIP;
+            }
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            set_last_hip_error((int)e);
+            return AFMM_ERR_HIP;
+        }
+        return AFMM_OK;
+    }
     hipLaunchKernelGGL(batch_schedule_kernel, dim3(1), dim3(1024), 0, s, pl->d_probs, count,
                        pl->d_isum, pl->d_order, pl->d_tile_start, pl->d_head);
     hipLaunchKernelGGL(batch_persistent_kernel, dim3(pl->persist_grid), dim3(kBW * 64), 0, s,
@@ -417,33 +451,56 @@ afmm_status enqueue(afmm_plan* pl, hipStream_t s) {
     return AFMM_OK;
 }
 
-bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
-    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-    return x < y + nb && y < x + na;
+// True when some output Z of the batch overlaps any X, Y or another Z of the
+// batch (inputs may share memory with each other).  Sort the address ranges by
+// start; a range overlaps an earlier one exactly when it starts below the
+// largest end seen so far, so track that end over all ranges and over the Z
+// ranges alone.
+bool batch_aliases(const afmm_problem* problems, int32_t count) {
+    struct Range {
+        uintptr_t lo, hi;
+        bool z;
+    };
+    std::vector<Range> r;
+    r.reserve(3 * (size_t)count);
+    for (int32_t p = 0; p < count; ++p) {
+        const size_t bytes = (size_t)problems[p].n * problems[p].n * 4;
+        r.push_back({reinterpret_cast<uintptr_t>(problems[p].X),
+                     reinterpret_cast<uintptr_t>(problems[p].X) + bytes, false});
+        r.push_back({reinterpret_cast<uintptr_t>(problems[p].Y),
+                     reinterpret_cast<uintptr_t>(problems[p].Y) + bytes, false});
+        r.push_back({reinterpret_cast<uintptr_t>(problems[p].Z),
+                     reinterpret_cast<uintptr_t>(problems[p].Z) + bytes, true});
+    }
+    std::sort(r.begin(), r.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+    uintptr_t end_all = 0, end_z = 0;
+    for (const Range& x : r) {
+        if (x.z ? x.lo < end_all : x.lo < end_z) return true;
+        end_all = std::max(end_all, x.hi);
+        if (x.z) end_z = std::max(end_z, x.hi);
+    }
+    return false;
 }
 
 }  // namespace
 
 extern "C" {
 
-afmm_status afmm_plan_create(const afmm_problem* problems, int32_t count, afmm_mode mode,
+afmm_status afmm_batched_plan_create(const afmm_problem* problems, int32_t count, afmm_mode mode,
                              afmm_plan** out) {
     if (!out || !problems || count < 1 || count > kMaxBatch) return AFMM_ERR_INVALID_ARG;
     *out = nullptr;
-    if (mode == AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_UNSUPPORTED;
-    if (mode != AFMM_MODE_STRICT) return AFMM_ERR_INVALID_ARG;
+    if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;
     for (int32_t p = 0; p < count; ++p) {
         const afmm_problem& q = problems[p];
         if ((q.case_id != AFMM_CASE_A && q.case_id != AFMM_CASE_B) || q.n < 1 ||
             q.n > AFMM_MAX_BATCH_N || !q.X || !q.Y || !q.Z)
             return AFMM_ERR_INVALID_ARG;
-        const size_t bytes = (size_t)q.n * q.n * 4;
-        if (overlaps(q.Z, bytes, q.X, bytes) || overlaps(q.Z, bytes, q.Y, bytes))
-            return AFMM_ERR_ALIAS;
         if ((reinterpret_cast<uintptr_t>(q.X) | reinterpret_cast<uintptr_t>(q.Y) |
              reinterpret_cast<uintptr_t>(q.Z)) & 3)
             return AFMM_ERR_INVALID_ARG;
     }
+    if (batch_aliases(problems, count)) return AFMM_ERR_ALIAS;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return AFMM_ERR_NO_DEVICE;
     hipDeviceProp_t prop;
@@ -486,13 +543,26 @@ afmm_status afmm_plan_create(const afmm_problem* problems, int32_t count, afmm_m
         rows += n;
         chunks += (b.ldp / 64) * (b.ldp / 64);
         tiles += (int64_t)b.tiles_r * b.tiles_c;
-        o_p8[p] = take((size_t)b.ldp * b.ldp);
-        o_q[p] = take((size_t)b.ldp * b.ldq * 4);
+        if (mode == AFMM_MODE_STRICT) {
+            o_p8[p] = take((size_t)b.ldp * b.ldp);
+            o_q[p] = take((size_t)b.ldp * b.ldq * 4);
+        }
     }
     const size_t o_wk = take(8 * (size_t)rows);
 
     afmm_plan* pl = new afmm_plan();
     pl->count = count;
+    pl->mode = mode;
+    if (mode == AFMM_MODE_SPLIT_BF16X3) {
+        pl->probs.assign(problems, problems + count);
+        pl->split_layouts.resize(count);
+        pl->split_off.resize(count);
+        for (int32_t p = 0; p < count; ++p) {
+            const int n = problems[p].n;
+            pl->split_layouts[p] = split_planes_layout(problems[p].case_id == AFMM_CASE_A, n, n, n);
+            pl->split_off[p] = take(pl->split_layouts[p].total);
+        }
+    }
     pl->device = dev;
     pl->total_chunks = chunks;
     pl->total_rows = rows;
@@ -505,7 +575,7 @@ afmm_status afmm_plan_create(const afmm_problem* problems, int32_t count, afmm_m
         return AFMM_ERR_HIP;
     }
     uint8_t* m = static_cast<uint8_t*>(pl->mem);
-    for (int32_t p = 0; p < count; ++p) {
+    for (int32_t p = 0; p < count && mode == AFMM_MODE_STRICT; ++p) {
         hp[p].P8 = m + o_p8[p];
         hp[p].Q = reinterpret_cast<float*>(m + o_q[p]);
     }
@@ -530,7 +600,7 @@ afmm_status afmm_plan_create(const afmm_problem* problems, int32_t count, afmm_m
     return AFMM_OK;
 }
 
-afmm_status afmm_plan_launch(afmm_plan* pl, hipStream_t stream) {
+afmm_status afmm_batched_plan_launch(afmm_plan* pl, hipStream_t stream) {
     if (!pl) return AFMM_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(pl->mu);
     if (!pl->exec) {
@@ -564,7 +634,7 @@ afmm_status afmm_plan_launch(afmm_plan* pl, hipStream_t stream) {
     return AFMM_OK;
 }
 
-afmm_status afmm_plan_problem_adds(const afmm_plan* pl, uint64_t* d_out, hipStream_t stream) {
+afmm_status afmm_batched_plan_problem_adds(const afmm_plan* pl, uint64_t* d_out, hipStream_t stream) {
     if (!pl || !d_out) return AFMM_ERR_INVALID_ARG;
     const hipError_t e = hipMemcpyAsync(d_out, pl->d_adds, 8 * (size_t)pl->count,
                                         hipMemcpyDeviceToDevice, stream);
@@ -575,7 +645,7 @@ afmm_status afmm_plan_problem_adds(const afmm_plan* pl, uint64_t* d_out, hipStre
     return AFMM_OK;
 }
 
-afmm_status afmm_plan_destroy(afmm_plan* pl) {
+afmm_status afmm_batched_plan_destroy(afmm_plan* pl) {
     if (!pl) return AFMM_ERR_INVALID_ARG;
     (void)hipDeviceSynchronize();
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
@@ -589,7 +659,7 @@ afmm_status afmm_plan_destroy(afmm_plan* pl) {
 afmm_status afmm_multiply_batched(const afmm_problem* problems, int32_t count, afmm_mode mode,
                                   hipStream_t stream) {
     afmm_plan* pl = nullptr;
-    afmm_status st = afmm_plan_create(problems, count, mode, &pl);
+    afmm_status st = afmm_batched_plan_create(problems, count, mode, &pl);
     if (st != AFMM_OK) return st;
     // one-shot: launch the sequence directly on the caller's stream (no graph)
     st = enqueue(pl, stream);
@@ -600,7 +670,7 @@ afmm_status afmm_multiply_batched(const afmm_problem* problems, int32_t count, a
             st = AFMM_ERR_HIP;
         }
     }
-    afmm_plan_destroy(pl);
+    afmm_batched_plan_destroy(pl);
     return st;
 }
 

@@ -323,3 +323,82 @@ hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, cons
 }
 
 }  // namespace afmm
+
+namespace afmm {
+
+// ---------------------------------------------------------------------------
+// Read-back of a converted plane in the factor's own orientation (for the
+// conversion's parity check): out[r][c] = plane[c][r] (TRANS) or plane[r][c].
+__global__ __launch_bounds__(256) void plane_unpack_kernel(const uint16_t* __restrict__ plane,
+                                                           int64_t ld, bool trans, int rows,
+                                                           int cols, uint16_t* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int64_t r = e / cols, c = e - r * cols;
+    out[e] = trans ? plane[c * ld + r] : plane[r * ld + c];
+}
+
+hipError_t launch_plane_unpack(const uint16_t* plane, int64_t ld, bool trans, int rows, int cols,
+                               uint16_t* out, hipStream_t s) {
+    const int64_t total = (int64_t)rows * cols;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(plane_unpack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, plane, ld,
+                       trans, rows, cols, out);
+    return hipGetLastError();
+}
+
+}  // namespace afmm
+
+namespace afmm {
+
+SplitLayout split_planes_layout(bool case_a, int m, int k, int n) {
+    SplitLayout L;
+    L.rows_real = split_real_rows_pad(case_a ? m : n);
+    L.rows_int = split_int_rows_pad(case_a ? n : m);
+    L.ld = round_up(k, 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = (off + bytes + 255) / 256 * 256;
+        return at;
+    };
+    for (int q = 0; q < 3; ++q) L.planes[q] = take((size_t)L.rows_real * L.ld * 2);
+    L.planes[3] = take((size_t)L.rows_int * L.ld * 2);
+    L.total = off;
+    return L;
+}
+
+hipError_t launch_split_prepare(bool case_a, int m, int k, int n, const void* X, int64_t ldx,
+                                const void* Y, int64_t ldy, const SplitLayout& L, uint8_t* base,
+                                hipStream_t s) {
+    // case A: X's three terms [i][k], Y as bf16 turned to [j][k];
+    // case B: X as bf16 [i][k], Y's three terms turned to [j][k]
+    SplitPrepArgs a;
+    a.I = static_cast<const int32_t*>(case_a ? Y : X);
+    a.i_rows = case_a ? k : m;
+    a.i_cols = case_a ? n : k;
+    a.ldi = case_a ? ldy : ldx;
+    a.ip = reinterpret_cast<uint16_t*>(base + L.planes[3]);
+    a.i_tiles_o = L.rows_int / 64;
+    a.R = static_cast<const float*>(case_a ? X : Y);
+    a.r_rows = case_a ? m : k;
+    a.r_cols = case_a ? k : n;
+    a.ldr = case_a ? ldx : ldy;
+    a.hi = reinterpret_cast<uint16_t*>(base + L.planes[0]);
+    a.mid = reinterpret_cast<uint16_t*>(base + L.planes[1]);
+    a.lo = reinterpret_cast<uint16_t*>(base + L.planes[2]);
+    a.r_tiles_o = L.rows_real / 64;
+    a.ld = L.ld;
+    a.int_blocks = (int)((int64_t)a.i_tiles_o * (L.ld / 64));
+    return launch_split_prep(case_a, a, s);
+}
+
+hipError_t launch_split_gemm(bool case_a, int m, int n, const SplitLayout& L, const uint8_t* base,
+                             float* Z, int64_t ldz, hipStream_t s) {
+    auto plane = [&](int q) { return reinterpret_cast<const uint16_t*>(base + L.planes[q]); };
+    return launch_gemm_bf16x3(case_a, m, n, plane(3), plane(0), plane(1), plane(2), L.ld, Z, ldz,
+                              s);
+}
+
+}  // namespace afmm

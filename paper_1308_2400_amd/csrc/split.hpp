@@ -30,7 +30,28 @@ hipError_t launch_split_prep(bool case_a, const SplitPrepArgs& a, hipStream_t s)
 hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, const uint16_t* S0,
                               const uint16_t* S1, const uint16_t* S2, int64_t ld, float* Z,
                               int64_t ldz, hipStream_t s);
+// out (rows x cols, row-major) = the plane read back: out[r][c] = plane[c][r]
+// (trans) or plane[r][c], plane pitch ld.
+hipError_t launch_plane_unpack(const uint16_t* plane, int64_t ld, bool trans, int rows, int cols,
+                               uint16_t* out, hipStream_t s);
 int split_real_rows_pad(int n);  // rows of a term plane
 int split_int_rows_pad(int n);   // rows of the integer plane
+
+// Workspace layout of a split product of an m x k real-or-integer pre-factor
+// and a k x n post-factor: K-contiguous bfloat16 planes; the real factor's three
+// terms have one row per i (case A) or per j (case B), the integer plane the other.
+struct SplitLayout {
+    int rows_real, rows_int;  // padded rows of the real-term planes and the integer plane
+    int64_t ld;               // K pitch
+    size_t planes[4], total;  // byte offsets: hi, mid, lo, then the integer plane
+};
+SplitLayout split_planes_layout(bool case_a, int m, int k, int n);
+// Conversion of X (m x k, pitch ldx) and Y (k x n, pitch ldy) into the planes at base.
+hipError_t launch_split_prepare(bool case_a, int m, int k, int n, const void* X, int64_t ldx,
+                                const void* Y, int64_t ldy, const SplitLayout& L, uint8_t* base,
+                                hipStream_t s);
+// Z (m x n, pitch ldz) from the planes at base.
+hipError_t launch_split_gemm(bool case_a, int m, int n, const SplitLayout& L, const uint8_t* base,
+                             float* Z, int64_t ldz, hipStream_t s);
 
 }  // namespace afmm

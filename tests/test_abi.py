@@ -28,8 +28,8 @@ def afmm():
 def test_header_declares_the_boundary():
     names = _header_functions()
     for must in ("afmm_multiply_caseA", "afmm_multiply_caseB", "afmm_multiply_batched",
-                 "afmm_count_adds", "afmm_validate", "afmm_plan_create", "afmm_plan_launch",
-                 "afmm_plan_destroy", "afmm_workspace_size", "afmm_status_string"):
+                 "afmm_count_adds", "afmm_validate", "afmm_batched_plan_create", "afmm_batched_plan_launch",
+                 "afmm_batched_plan_destroy", "afmm_workspace_size", "afmm_status_string"):
         assert must in names
 
 

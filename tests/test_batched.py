@@ -63,6 +63,79 @@ def test_batched_mixed_bitexact_and_counts(dev):
     plan.close()
 
 
+def test_batched_large_tiles_bitexact(dev):
+    """Problems of n >= 512 (the batch's widest tile body) mixed with small ones,
+    every element bit for bit: both cases, counts up to 400 (escape path) and
+    negative counts."""
+    r = np.random.default_rng(17)
+    probs = []
+    for t, n in enumerate([512, 530, 601, 700, 577, 33, 129]):
+        case = "AB"[t % 2]
+        real = r.standard_normal((n, n)).astype(np.float32)
+        real[r.random((n, n)) > r.uniform(0.1, 1)] = 0
+        ints = r.integers(0, [3, 63, 400, 15, 255, 9, 7][t] + 1, (n, n)).astype(np.int32)
+        ints[r.random((n, n)) > r.uniform(0.1, 1)] = 0
+        if t == 2:
+            ints[::3, ::2] *= -1
+        probs.append((case, *((real, ints) if case == "A" else (ints, real))))
+    plan, dprobs = _run_plan(dev, probs)
+    plan.launch()
+    adds = plan.problem_adds()
+    for t, ((case, X, Y), (*_, Zd)) in enumerate(zip(probs, dprobs)):
+        Zref, a = oracle.strict_f32_threaded(case, X, Y)
+        Z = Zd.cpu().numpy()
+        assert np.array_equal(Z.view(np.uint32), Zref.view(np.uint32)), (t, case, X.shape)
+        assert adds[t] == a, t
+    plan.close()
+
+
+def test_batched_split_mode(dev):
+    """Split-mode plans: each product equals the single-product split call, and
+    the per-problem counts are the exact ones."""
+    import torch
+    import paper_1308_2400_amd as afmm
+    r = np.random.default_rng(5)
+    probs = []
+    for t, n in enumerate([1, 40, 257, 300, 64]):
+        case = "AB"[t % 2]
+        real = r.standard_normal((n, n)).astype(np.float32)
+        ints = r.integers(0, 257, (n, n)).astype(np.int32)
+        probs.append((case, *((real, ints) if case == "A" else (ints, real))))
+    dprobs = []
+    for case, X, Y in probs:
+        Zd = torch.full((X.shape[0], X.shape[0]), float("nan"), dtype=torch.float32, device=dev)
+        dprobs.append((case, _to(dev, X), _to(dev, Y), Zd))
+    plan = afmm.Plan(dprobs, mode="split")
+    for _ in range(2):  # the captured graph, then its replay
+        plan.launch()
+        adds = plan.problem_adds()
+        for t, ((case, X, Y), (_, Xd, Yd, Zd)) in enumerate(zip(probs, dprobs)):
+            single = afmm.multiply(case, Xd, Yd, "split")
+            assert torch.equal(single.view(torch.int32), Zd.view(torch.int32)), t
+            assert oracle.rel_frobenius(Zd.cpu().numpy(), oracle.product_f64(case, X, Y)) <= 1e-6
+            assert adds[t] == oracle.count(case, X, Y)[0], t
+    plan.close()
+
+
+def test_batched_alias_across_problems(dev):
+    """An output that overlaps another problem's input or output is refused."""
+    import ctypes
+    import torch
+    import paper_1308_2400_amd as afmm
+    buf = torch.zeros(4 * 64, dtype=torch.float32, device=dev)
+    Y = torch.zeros((8, 8), dtype=torch.int32, device=dev)
+    p = lambda x, y, z: afmm.afmm_problem(0, 8, x, y, z)  # noqa: E731
+    a, b, c, d = (buf.data_ptr() + 256 * t for t in range(4))
+    h = ctypes.c_void_p()
+    ok = (afmm.afmm_problem * 2)(p(a, Y.data_ptr(), b), p(a, Y.data_ptr(), c))  # shared X: fine
+    assert afmm.afmm_batched_plan_create(ok, 2, 0, ctypes.byref(h)) == 0
+    afmm.afmm_batched_plan_destroy(h)
+    bad = (afmm.afmm_problem * 2)(p(a, Y.data_ptr(), b), p(c, Y.data_ptr(), a))  # Z_2 = X_1
+    assert afmm.afmm_batched_plan_create(bad, 2, 0, ctypes.byref(h)) == 2
+    bad = (afmm.afmm_problem * 2)(p(a, Y.data_ptr(), c), p(b, Y.data_ptr(), c + 128))  # Zs overlap
+    assert afmm.afmm_batched_plan_create(bad, 2, 0, ctypes.byref(h)) == 2
+
+
 def test_batched_graph_replays_identical(dev):
     import torch
     probs = _mixed_problems(25, 2, n_max=200)
@@ -116,12 +189,12 @@ def test_batched_errors(dev):
     Z = torch.zeros((8, 8), dtype=torch.float32, device=dev)
     arr = (afmm.afmm_problem * 1)(afmm.afmm_problem(0, 8, X.data_ptr(), Y.data_ptr(), Z.data_ptr()))
     h = ctypes.c_void_p()
-    assert afmm.afmm_plan_create(arr, 1, 1, ctypes.byref(h)) == 8  # split: unsupported
-    assert afmm.afmm_plan_create(arr, 0, 0, ctypes.byref(h)) == 1
+    assert afmm.afmm_batched_plan_create(arr, 1, 2, ctypes.byref(h)) == 1  # no such mode
+    assert afmm.afmm_batched_plan_create(arr, 0, 0, ctypes.byref(h)) == 1
     arr[0].Z = X.data_ptr()
-    assert afmm.afmm_plan_create(arr, 1, 0, ctypes.byref(h)) == 2  # Z aliases X
+    assert afmm.afmm_batched_plan_create(arr, 1, 0, ctypes.byref(h)) == 2  # Z aliases X
     arr[0].n = 0
-    assert afmm.afmm_plan_create(arr, 1, 0, ctypes.byref(h)) == 1
+    assert afmm.afmm_batched_plan_create(arr, 1, 0, ctypes.byref(h)) == 1
 
 
 def test_batched_512_sampled(dev):

@@ -496,3 +496,13 @@ def test_rect_leading_dimensions_in_c():
                                            tot.ctypes.data, rows.ctypes.data)
     assert fl == 0 and int(tot[0]) == ac
     del ctypes
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_threaded_oracle_equals_single_call(case):
+    """Row ranges on several threads give the single call's bits and count."""
+    X, Y = _rng_case(case, 203, 77, int_hi=9, dyadic=False)
+    Z1, a1 = oracle.strict_f32(case, X, Y)
+    Z2, a2 = oracle.strict_f32_threaded(case, X, Y, threads=7)
+    assert a1 == a2
+    assert np.array_equal(Z1.view(np.uint32), Z2.view(np.uint32))

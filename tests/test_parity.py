@@ -209,6 +209,28 @@ def test_caseB_n4096_sampled(dev):
     _check_strict(dev, "B", X, Y, rows=_sample_rows(4096, 16))
 
 
+@pytest.fixture(scope="module")
+def c3_full():
+    """The whole n=4096 case-B workload and the oracle's result for all of it
+    (the oracle over disjoint row ranges on the host's threads)."""
+    w = gen.caseB_n4096()
+    X, Y = w.X(), w.Y()
+    Zref, adds = oracle.strict_f32_threaded("B", X, Y)
+    return X, Y, Zref, adds
+
+
+@pytest.mark.parametrize("cfg", [None, (3, 2, 16, 16, 2, 8), (0, 4, 16, 16, 1, 16)], ids=str)
+def test_caseB_n4096_full_matrix(dev, c3_full, cfg):
+    """Every element of the n=4096 case-B product, bit for bit, in the library's
+    default configuration (the benchmark's launch) and two others."""
+    X, Y, Zref, adds = c3_full
+    afmm = _afmm()
+    Z = afmm.multiply("B", _to(dev, X), _to(dev, Y), "strict", config=cfg).cpu().numpy()
+    assert _bits_equal(Z, Zref), _first_diff(Z, Zref)
+    if cfg is None:
+        assert afmm.count_adds("B", _to(dev, X), _to(dev, Y)) == adds
+
+
 @pytest.mark.parametrize("cfg", SPARSE, ids=str)
 def test_caseB_n4096_sampled_sparse(dev, cfg):
     w = gen.caseB_n4096()

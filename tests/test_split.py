@@ -100,3 +100,49 @@ def test_split_vs_strict_same_ballpark(dev, case):
     Z64 = oracle.product_f64(case, X, Y)
     assert oracle.rel_frobenius(Zm, Z64) <= TOL
     assert oracle.rel_frobenius(Zs, Z64) < 1e-5
+
+
+def _golden_split_values():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "split_bf16x3.json")
+    with open(path) as f:
+        return [np.float32(float.fromhex(c["x"])) for c in json.load(f)["cases"]]
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("n", [1, 7, 67, 200])
+def test_split_terms_match_oracle_bitwise(dev, case, n):
+    """The GPU conversion pass gives the oracle's hi/mid/lo patterns for every
+    real entry (hand-worked rounding cases planted among normal, tiny and zero
+    values) and the exact bfloat16 of every integer entry (<= 0 becomes +0)."""
+    import ctypes
+    import torch
+    import paper_1308_2400_amd as afmm
+    r = np.random.default_rng(900 + n)
+    real = r.standard_normal((n, n)).astype(np.float32)
+    flat = real.reshape(-1)
+    gold = _golden_split_values()
+    for t, v in enumerate(gold):
+        if t < flat.size:
+            flat[(t * 37) % flat.size] = v
+    flat[r.random(flat.size) < 0.2] = 0.0
+    flat[r.random(flat.size) < 0.1] *= np.float32(2.0 ** -60)
+    ints = r.integers(-3, 257, (n, n)).astype(np.int32)
+    X, Y = (real, ints) if case == "A" else (ints, real)
+    Xd, Yd = _to(dev, X), _to(dev, Y)
+    terms = torch.empty((3, n, n), dtype=torch.int16, device=dev)
+    ibf = torch.empty((n, n), dtype=torch.int16, device=dev)
+    st = afmm.afmm_split_terms(0 if case == "A" else 1, n, Xd.data_ptr(), Yd.data_ptr(),
+                               terms.data_ptr(), ibf.data_ptr(), None, 0,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    got = terms.cpu().numpy().view(np.uint16)
+    hi, mid, lo = oracle.split_bf16x3(real)
+    assert np.array_equal(got[0], hi)
+    assert np.array_equal(got[1], mid)
+    assert np.array_equal(got[2], lo)
+    # integers: exact in bfloat16 up to 256 (an integer below 2^8 has at most 8
+    # significant bits; 256 is a power of two), counts <= 0 contribute nothing
+    want = (np.maximum(ints, 0).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    assert np.array_equal(ibf.cpu().numpy().view(np.uint16), want)
