@@ -84,6 +84,36 @@ def per_launch_ms(fn, launches, stream):
     return t[len(t) // 2], t[0]
 
 
+def host_info():
+    """Host CPU facts for the baseline: model, logical CPUs, the CPUs this process may
+    run on, and the thread count the baseline uses (a GPU's share of the box is 16)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"cpu_model": model, "nproc_logical": os.cpu_count(), "cpus_allowed": allowed,
+            "threads_used": baseline_threads()}
+
+
+def baseline_threads():
+    """Threads for the CPU baseline: the CPUs this process may use, capped at 16 (the
+    host-CPU share one GPU of the box comes with)."""
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return max(1, min(16, allowed))
+
+
 def cpu_baseline(w, X, Y, seconds):
     """The oracle as it stands on a bounded sample of rows: one thread, then the same
     function over disjoint row ranges on the host's cores (rows are independent; the
@@ -105,7 +135,7 @@ def cpu_baseline(w, X, Y, seconds):
     _, adds1 = oracle.strict_f32(w.case, X[rows], Y, rows=rows, x_rows_only=True)
     dt1 = time.perf_counter() - t
     # the same function on P threads, each a contiguous chunk of the sample
-    P = max(1, min(16, os.cpu_count() or 1))
+    P = baseline_threads()
     kp = max(P, min(w.n, int(0.5 * seconds * P / per_row)))
     chunks = np.array_split(rows_all[:kp], P)
 
@@ -117,6 +147,10 @@ def cpu_baseline(w, X, Y, seconds):
         addsp = sum(ex.map(run, chunks))
     dtp = time.perf_counter() - t
     return {"value": addsp / dtp, "unit": "useful adds/s", "cores": P, "kind": "oracle",
+            "host": host_info(),
+            "paper_context": "Table 1, one Pentium at 1.6 GHz (Section 2.3.1): the case-A loop at "
+                             "n=2000 took 53.4 s (mu'=1) to 145.9 s (mu'=7), 2.5e7 to 1.1e8 "
+                             "additions/s; a different workload and machine",
             "sample": f"{kp} of {w.n} rows of the same workload over {P} threads "
                       f"({addsp} additions, {dtp:.1f} s)",
             "single_thread": {"value": adds1 / dt1, "cores": 1,
@@ -152,7 +186,7 @@ def measured_traffic(config):
     return d.get("hbm_bytes_per_launch")
 
 
-def bench_batched(args, stream, single_issued_frac):
+def bench_batched(args, stream, single_issued_frac, single_useful_per_s):
     """512 products of uneven n, density and integer range: one plan, graph replays."""
     import numpy as np
     import torch
@@ -180,6 +214,24 @@ def bench_batched(args, stream, single_issued_frac):
     torch.cuda.synchronize()
     ms = event_time_ms(plan.launch, args.steps, stream)
     adds = sum(plan.problem_adds())
+    # the same 512 products as separate single-product calls (the library's own
+    # choice of kernel per product, one workspace reused), one after another
+    ws = torch.empty(max(afmm.workspace_size(case, X.shape[0], "strict") for case, X, _ in host),
+                     dtype=torch.uint8, device=dev)
+    sp = stream.cuda_stream
+    zs = [torch.empty_like(Z) for *_, Z in probs]
+
+    def separate():
+        for (case, Xd, Yd, _), Z2 in zip(probs, zs):
+            f = afmm.afmm_multiply_caseA if case == "A" else afmm.afmm_multiply_caseB
+            st = f(Xd.shape[0], Xd.data_ptr(), Yd.data_ptr(), Z2.data_ptr(), 0, ws.data_ptr(),
+                   ws.numel(), sp)
+            assert st == 0
+    separate()
+    torch.cuda.synchronize()
+    sep_ms = event_time_ms(separate, max(1, min(args.steps, 5)), stream)
+    same = all(torch.equal(a.view(torch.int32), b[3].view(torch.int32)) for a, b in zip(zs, probs))
+    del zs, ws
     # spot parity: first row of a few products
     ok = True
     for t in (0, 1, len(host) // 2, len(host) - 1):
@@ -188,22 +240,76 @@ def bench_batched(args, stream, single_issued_frac):
         ok &= bool(np.array_equal(probs[t][3][:1].cpu().numpy().view(np.uint32), Zr.view(np.uint32)))
     frac = issued / (ms * 1e-3) / 1e12 / SINGLE_ISSUE_TADDS
     plan.close()
-    log(f"bench: batched {ms:.3f} ms, {adds / (ms * 1e-3):.3e} adds/s, issued frac {frac:.3f}")
+    log(f"bench: batched {ms:.3f} ms, {adds / (ms * 1e-3):.3e} adds/s, issued frac {frac:.3f}; "
+        f"separate launches {sep_ms:.3f} ms")
     return {"workload": "512 products, n log-uniform [32,1024], d1,d2 ~ U(0.05,1), "
                         "integer U{0..R}, R in {3,15,63,255}, real U(-1,1)",
             "ms": ms, "useful_adds": adds, "useful_adds_per_s": adds / (ms * 1e-3),
+            "separate_launches_ms": sep_ms,
+            "separate_launches_useful_adds_per_s": adds / (sep_ms * 1e-3),
+            # the same products, the same additions: useful adds/s of the one batched
+            # launch over that of the products as separate calls
+            "efficiency_vs_separate_launches": sep_ms / ms,
+            "separate_launches_bit_identical": bool(same),
+            # useful adds/s over that of the single n=4096 product
+            "useful_rate_vs_single_launch": adds / (ms * 1e-3) / single_useful_per_s,
             "issued_lane_adds": issued,
             "issued_frac_of_single_issue_rate": frac,
-            "efficiency_vs_single_launch": frac / single_issued_frac,
+            "issued_rate_vs_single_launch": frac / single_issued_frac,
             "bitexact_sampled_rows": ok,
-            "timed": "whole plan launch (graph replay: prep, count, schedule, persistent kernel)"}
+            "timed": "whole plan launch (graph replay: prep, count, schedule, persistent kernel); "
+                     "separate: 512 afmm_multiply_caseA/B calls in a row"}
 
 
-TABLE1_N = (250, 500, 750, 1000, 1250, 1500, 1750, 2000)
-TABLE1_MU = (1, 3, 5, 7, 14, 21)
-# the paper's Table 1 times (seconds, Pentium 1.6 GHz, single thread) for context
-TABLE1_PAPER_2000 = {"ikj": 147.078, 1: 53.375, 3: 94.6875, 5: 120.8515, 7: 145.8985,
-                     14: 119.516, 21: 122.491}
+def add_rate_probe(stream):
+    """The device's binary32 add rate on straight-line v_add_f32 runs (the library's
+    probe kernel, one block per compute unit) at 1, 2 and 4 waves per SIMD: the
+    measured denominator beside the nominal one."""
+    import ctypes
+
+    import torch
+    import paper_1308_2400_amd as afmm
+    out = torch.empty(1024, dtype=torch.float32, device="cuda")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res = {}
+    for wps in (1, 2, 4):
+        adds = ctypes.c_uint64()
+
+        def go():
+            st = afmm.afmm_probe_add_rate(wps, 4000, out.data_ptr(), ctypes.byref(adds),
+                                          stream.cuda_stream)
+            assert st == 0
+        for _ in range(20):  # settle the clock
+            go()
+        ms = event_time_ms(go, 10, stream)
+        rate = adds.value / (ms * 1e-3)
+        res[f"{wps}_waves_per_simd"] = {
+            "adds_per_s": rate, "frac_of_nominal_peak": rate / 1e12 / PEAK_ADD_TFLOPS,
+            "lane_adds_per_clk_per_cu_at_2.4GHz": rate / (cus * 2.4e9)}
+    res["compute_units"] = cus
+    res["kernel"] = "add_rate_probe_kernel: 16 accumulators x 8 adds per trip, 4000 trips"
+    res["note"] = ("one wave issues at most one VALU instruction per 4 cycles; the doubled "
+                   "binary32 rate needs two waves ready to issue on a SIMD")
+    return res
+
+
+# the paper's Table 1 (seconds, one Pentium at 1.6 GHz, single thread), for context:
+# n -> (ijk, ikj, AFMM at mu' = 1, 3, 5, 7, 14, 21)
+TABLE1_PAPER = {
+    250: (0.411667, 0.328, 0.1752, 0.2784, 0.3316, 0.3498, 0.3188, 0.2874),
+    500: (2.718667, 2.32, 0.918, 1.5406, 1.943, 2.331, 1.9122, 1.9874),
+    750: (10.235, 7.75533, 2.8475, 4.9718, 6.38, 7.6826, 6.3218, 6.4328),
+    1000: (25.125, 18.43233, 6.67175, 11.8064, 15.073, 18.2756, 14.9158, 15.3374),
+    1250: (49.437, 35.75, 13.0897, 23.0705, 29.489, 35.594, 29.172, 29.9267),
+    1500: (85.531, 61.688, 22.5625, 40.078, 50.9295, 61.718, 50.3515, 52.2),
+    1750: (135.906, 98.515, 36.0235, 63.2655, 80.6235, 97.6955, 80.281, 81.9335),
+    2000: (205.422, 147.078, 53.375, 94.6875, 120.8515, 145.8985, 119.516, 122.491),
+}
+
+
+def paper_seconds(n, mu):
+    """The paper's Table 1 time for AFMM at (n, mu'), seconds."""
+    return TABLE1_PAPER[n][2 + (1, 3, 5, 7, 14, 21).index(mu)]
 
 
 def empirical_fit(rows):
@@ -321,15 +427,11 @@ def table1(args):
     import paper_1308_2400_amd as afmm
     stream = torch.cuda.current_stream()
     rows = []
-    for n in TABLE1_N:
-        for mu in TABLE1_MU:
-            d1, d2 = (1 / 3, 1 / 2) if mu <= 7 else (1 / 5, 2 / 5)
+    for n in gen.TABLE1_N:
+        for mu in gen.TABLE1_MU:
             for ydist in ("const", "uniform"):
-                ispec = (gen.IntSpec(gen.INT_UNIFORM, d2, mu, mu) if ydist == "const"
-                         else gen.IntSpec(gen.INT_UNIFORM, d2, 1, 2 * mu - 1))
-                w = gen.Workload(f"table1_n{n}_mu{mu}_{ydist}", "A", n,
-                                 gen.RealSpec(gen.UNIFORM01, d1), ispec, gen.SEED0 + 6,
-                                 100 * mu + (1 if ydist == "uniform" else 0))
+                w = gen.table1(n, mu, ydist)
+                d1, d2 = w.real.density, w.int_.density
                 X, Y = w.X(), w.Y()
                 Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
                 Z = afmm.multiply("A", Xd, Yd)
@@ -338,7 +440,8 @@ def table1(args):
                                    stream)
                 r = {"n": n, "mu_prime": mu, "d1": d1, "d2": d2, "y_nonzeros": ydist,
                      "adds": adds, "expected_adds": w.expected_adds(), "gpu_ms": ms,
-                     "adds_per_s": adds / (ms * 1e-3)}
+                     "adds_per_s": adds / (ms * 1e-3),
+                     "paper_pentium_s": paper_seconds(n, mu)}
                 if n == 250:  # the oracle (single thread) for the smallest size, bit for bit
                     t = time.perf_counter()
                     Zr, a2 = oracle.caseA_f32(X, Y)
@@ -349,7 +452,7 @@ def table1(args):
                 log(f"table1 n={n} mu'={mu} {ydist}: {ms:.3f} ms, {adds:.3e} adds")
     out = {"metric": "Table 1 grid (case A): strict AFMM time per product", "unit": "ms",
            "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded generator)",
-           "paper_n2000_seconds_pentium": {str(k): v for k, v in TABLE1_PAPER_2000.items()},
+           "paper_table1_seconds_pentium": {str(k): v for k, v in TABLE1_PAPER.items()},
            "empirical_fit": empirical_fit(rows), "rows": rows}
     print(json.dumps(out), flush=True)
 
@@ -534,6 +637,11 @@ def main():
                                + " (strict, one launch = one n=4096 product)"},
     }
 
+    out["add_peak_probe"] = add_rate_probe(stream)
+    log("bench: add-rate probe " + ", ".join(
+        f"{k} {v['frac_of_nominal_peak']:.3f}" for k, v in out["add_peak_probe"].items()
+        if isinstance(v, dict)))
+
     if not args.no_split:
         Zs = torch.empty_like(Z)
 
@@ -558,7 +666,8 @@ def main():
         log(f"bench: split {split_ms:.3f} ms err {err:.2e}")
 
     if not args.no_batched:
-        out["batched"] = bench_batched(args, stream, out["strict"]["issued_frac_of_single_issue_rate"])
+        out["batched"] = bench_batched(args, stream, out["strict"]["issued_frac_of_single_issue_rate"],
+                                       out["strict"]["useful_adds_per_s"])
 
     if not args.no_cpu_baseline:
         log("bench: cpu baseline")

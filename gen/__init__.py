@@ -217,3 +217,23 @@ def batched_512(count: int = 512, n_lo: int = 32, n_hi: int = 1024):
         out.append(Workload(f"batch{b}", case, n, RealSpec(UNIFORMPM1, d_real),
                             IntSpec(INT_UNIFORM, d_int, 0, R), seed, b))
     return out
+
+
+TABLE1_N = (250, 500, 750, 1000, 1250, 1500, 1750, 2000)
+TABLE1_MU = (1, 3, 5, 7, 14, 21)
+
+
+def table1(n: int, mu: int, y_nonzeros: str) -> Workload:
+    """One cell of the paper's Table 1 grid (Section 2.3.1): case A, X ~ U(0,1);
+    d1 = 1/3, d2 = 1/2 for mu' <= 7 and d1 = 1/5, d2 = 2/5 for mu' = 14, 21.  The
+    distribution of Y's non-zeros is not stated; two readings: 'const' (every
+    non-zero equals mu') and 'uniform' (U{1..2 mu' - 1}, mean mu')."""
+    d1, d2 = (1 / 3, 1 / 2) if mu <= 7 else (1 / 5, 2 / 5)
+    if y_nonzeros == "const":
+        ispec = IntSpec(INT_UNIFORM, d2, mu, mu)
+    elif y_nonzeros == "uniform":
+        ispec = IntSpec(INT_UNIFORM, d2, 1, 2 * mu - 1)
+    else:
+        raise ValueError(y_nonzeros)
+    return Workload(f"table1_n{n}_mu{mu}_{y_nonzeros}", "A", n, RealSpec(UNIFORM01, d1), ispec,
+                    SEED0 + 6, 100 * mu + (1 if y_nonzeros == "uniform" else 0))

@@ -180,9 +180,8 @@ afmm_status afmm_validate(afmm_case c, int64_t n, const void *X, const void *Y, 
  *   mapping: 0 = rep-uniform (each wave walks R rows of the integer factor
  *            with the count in a scalar register; lanes over the real
  *            factor's columns; case A runs on the transposed problem),
- *            1 = base-uniform (case A only: each wave walks R rows of X with
- *            the base in a scalar register; lanes over Y's columns with a
- *            per-lane count; not compiled into the library),
+ *            (1 is not used: a base-uniform mapping with per-lane counts,
+ *            rejected for its SIMD efficiency),
  *            2 = rep-uniform with base rows streamed straight into
  *            registers (no LDS panel); falls back to 0 when the base rows
  *            are not readable in 16-byte units (case B with n % 4 != 0),
@@ -325,6 +324,19 @@ afmm_status afmm_batched_plan_destroy(afmm_plan *plan);
 /* One-shot convenience: create, launch on `stream`, wait, destroy. */
 afmm_status afmm_multiply_batched(const afmm_problem *problems, int32_t count, afmm_mode mode,
                                   hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostic: the device's binary32 add rate, the denominator of the strict
+ * kernels' roofline.  Queues one launch of straight-line v_add_f32 runs (VGPR
+ * operands, 16 independent accumulators per lane, 128 additions per loop trip,
+ * `trips` trips), one block of 4 * waves_per_simd waves (1, 2 or 4) per compute
+ * unit, so each SIMD runs waves_per_simd waves.  d_out: 1024 floats of device
+ * memory (results, kept so the additions are not removed).  *adds (host) is
+ * set to the number of binary32 additions the launch performs; time the
+ * launch with events on `stream`.  Computes nothing of the method.
+ */
+afmm_status afmm_probe_add_rate(int32_t waves_per_simd, int32_t trips, float *d_out,
+                                uint64_t *adds, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 const char *afmm_status_string(afmm_status s);

@@ -23,10 +23,11 @@ static inline int64_t row_of(const int64_t *rows, int64_t t)
 }
 
 /*
- * Section 2, Case-A loop: for each row I, for each K, Base = X[I,K]; a zero
- * Base moves on to the next K; otherwise for each J, Rep-factor = Y[K,J] and
- * Z[I,J] receives Base that many times (readings R1, R3-R7; the I, K and J
- * bounds m, kd, n taken separately, reading R9).
+ * Case A (Section 2): X real, Y integer.  Every element starts at +0.0 and,
+ * for k ascending, receives the real entry X[i,k] added to it Y[k,j] times,
+ * one binary32 addition after another, straight into the element; a zero
+ * X[i,k] contributes nothing (readings R1, R3-R7; separate extents m, kd, n,
+ * reading R9).  Rows of Z are computed one after another.
  */
 uint64_t afmm_oracle_caseA_f32_ex(int64_t m, int64_t kd, int64_t n, const float *X, int64_t ldx,
                                   const int32_t *Y, int64_t ldy, float *Z, int64_t ldz,
@@ -39,15 +40,15 @@ uint64_t afmm_oracle_caseA_f32_ex(int64_t m, int64_t kd, int64_t n, const float 
         const int64_t i = row_of(rows, t);
         const float *xrow = X + (x_rows_only ? t : i) * ldx;
         float *zrow = Z + t * ldz;
-        for (int64_t j = 0; j < n; ++j) zrow[j] = 0.0f;          /* Z starts at zero */
+        for (int64_t j = 0; j < n; ++j) zrow[j] = 0.0f;
         for (int64_t k = 0; k < kd; ++k) {
-            const float base = xrow[k];
-            if (base == 0.0f) continue;                            /* zero Base: next K */
+            const float x = xrow[k];
+            if (x == 0.0f) continue;                               /* adds nothing */
             const int32_t *yrow = Y + k * ldy;
             for (int64_t j = 0; j < n; ++j) {
-                const int32_t rep = yrow[j];                       /* Rep-factor */
-                for (int32_t p = 0; p < rep; ++p) {
-                    zrow[j] = zrow[j] + base;                      /* one addition */
+                const int32_t times = yrow[j];                     /* <= 0: none */
+                for (int32_t p = 0; p < times; ++p) {
+                    zrow[j] = zrow[j] + x;                         /* one addition */
                     ++adds;
                 }
             }
@@ -64,10 +65,11 @@ uint64_t afmm_oracle_caseA_f32(int64_t n, const float *X, const int32_t *Y,
 }
 
 /*
- * Section 2, Case-B loop: Rep-factor = X[I,K]; for each J, Base = Y[K,J]; a
- * zero Base is skipped for that J only (reading R2); otherwise Z[I,J]
- * receives Base Rep-factor times.  A Rep-factor <= 0 adds nothing for any J
- * (reading R5), so testing it once per K changes no result and no count.
+ * Case B (Section 2): X integer, Y real.  Every element starts at +0.0 and,
+ * for k ascending, receives the real entry Y[k,j] added to it X[i,k] times,
+ * one binary32 addition after another; a zero Y[k,j] contributes nothing to
+ * that element only (reading R2), and a count <= 0 nothing at all (reading
+ * R5), which is why the count is tested once per k.
  */
 uint64_t afmm_oracle_caseB_f32_ex(int64_t m, int64_t kd, int64_t n, const int32_t *X, int64_t ldx,
                                   const float *Y, int64_t ldy, float *Z, int64_t ldz,
@@ -82,14 +84,14 @@ uint64_t afmm_oracle_caseB_f32_ex(int64_t m, int64_t kd, int64_t n, const int32_
         float *zrow = Z + t * ldz;
         for (int64_t j = 0; j < n; ++j) zrow[j] = 0.0f;
         for (int64_t k = 0; k < kd; ++k) {
-            const int32_t rep = xrow[k];                           /* Rep-factor */
-            if (rep <= 0) continue;
+            const int32_t times = xrow[k];
+            if (times <= 0) continue;
             const float *yrow = Y + k * ldy;
             for (int64_t j = 0; j < n; ++j) {
-                const float base = yrow[j];                        /* Base */
-                if (base == 0.0f) continue;                        /* skip this J only */
-                for (int32_t p = 0; p < rep; ++p) {
-                    zrow[j] = zrow[j] + base;
+                const float y = yrow[j];
+                if (y == 0.0f) continue;                           /* this element only */
+                for (int32_t p = 0; p < times; ++p) {
+                    zrow[j] = zrow[j] + y;                         /* one addition */
                     ++adds;
                 }
             }

@@ -191,8 +191,6 @@ bool config_ok(afmm_case c, const afmm_config& g) {
     if (g.mapping == 7) return rep_rows_supported(g.rows_per_wave, g.cols_per_lane, g.waves, u, kp);
     if (kp != 16) return false;
     if (u != 1) return false;
-    if (g.mapping == 1)
-        return c == AFMM_CASE_A && base_uniform_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
     if (g.mapping == 2) return rep_direct_supported(g.rows_per_wave, g.cols_per_lane, g.waves);
     return false;
 }
@@ -299,7 +297,7 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
                                     d.unroll == 0 ? 1 : d.unroll,
                                     d.k_panel == 0 ? 16 : d.k_panel, s));
     } else {
-        return AFMM_ERR_UNSUPPORTED;  // mapping 1 is not compiled (config_ok rejects it)
+        return AFMM_ERR_UNSUPPORTED;  // config_ok admits no other mapping
     }
     return AFMM_OK;
 }

@@ -96,13 +96,5 @@ hipError_t launch_rep_sparse(const StrictArgs& a, int R, int C, int W, int U, in
 bool rep_sparse_supported(int R, int C, int W, int U, int KP);
 bool rep_sparse_usable(const StrictArgs& a);  // float4 rows, 31-bit byte offsets
 
-struct BaseUniformArgs {
-    int n;
-    const float* X;          // rows i, base X[i,k] (wave-uniform)
-    const int32_t* Y;        // per-lane counts Y[k,j]
-    float* Z;
-};
-hipError_t launch_base_uniform(const BaseUniformArgs& a, int R, int C, int W, hipStream_t s);
-bool base_uniform_supported(int R, int C, int W);
 
 }  // namespace afmm

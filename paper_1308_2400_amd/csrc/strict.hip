@@ -52,10 +52,4 @@ hipError_t launch_rep_direct(const StrictArgs& a, int R, int C, int W, hipStream
     return hipErrorInvalidValue;
 }
 
-bool base_uniform_supported(int, int, int) { return false; }
-
-hipError_t launch_base_uniform(const BaseUniformArgs&, int, int, int, hipStream_t) {
-    return hipErrorInvalidValue;
-}
-
 }  // namespace afmm
