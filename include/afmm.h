@@ -326,6 +326,26 @@ afmm_status afmm_multiply_batched(const afmm_problem *problems, int32_t count, a
                                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the strict
+ * product of afmm_multiply_caseA / afmm_multiply_caseB (same kernels, same
+ * bits), with its workspace in a fixed array of AFMM_NOALLOC_SCRATCH_BYTES
+ * that the library keeps on every device it runs on, for the life of the
+ * process.  The call performs no allocation.  X, Y, Z and their layout are as
+ * for the square calls (case A: X binary32, Y int32; case B the other way).
+ * Returns AFMM_ERR_WORKSPACE when the product's workspace
+ * (afmm_workspace_size(c, n, AFMM_MODE_STRICT)) exceeds the array; with the
+ * built-in configurations that admits case B up to n = 9984 and case A up to
+ * n = 4480.  All calls on one device share its array and every call rewrites
+ * what it uses: calls that overlap in time on one device (different streams,
+ * or host threads racing) race on it and are not allowed.
+ */
+#define AFMM_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+
+afmm_status afmm_multiply_noalloc(afmm_case c, int64_t n, const void *X, const void *Y, float *Z,
+                                  hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Diagnostic: the device's binary32 add rate, the denominator of the strict
  * kernels' roofline.  Queues one launch of straight-line v_add_f32 runs (VGPR
  * operands, 16 independent accumulators per lane, 128 additions per loop trip,

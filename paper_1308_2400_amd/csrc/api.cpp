@@ -358,6 +358,21 @@ afmm_status count_adds(afmm_case c, const Shape& p, const void* X, const void* Y
 
 }  // namespace
 
+namespace afmm {
+
+afmm_status strict_product_in(afmm_case c, int64_t n, const void* X, const void* Y, float* Z,
+                              void* ws, size_t ws_bytes, hipStream_t s) {
+    if (c != AFMM_CASE_A && c != AFMM_CASE_B) return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_args(square(n), X, Y, Z);
+    if (st != AFMM_OK) return st;
+    if ((st = check_device()) != AFMM_OK) return st;
+    const afmm_config cfg = afmm_default_config(c, n);
+    if (strict_layout(c, square(n), cfg).total > ws_bytes) return AFMM_ERR_WORKSPACE;
+    return strict_run(c, square(n), X, Y, Z, cfg, ws, ws_bytes, s);
+}
+
+}  // namespace afmm
+
 extern "C" {
 
 size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode) {
