@@ -25,7 +25,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kTI = 256;  // block rows on the integer side
-constexpr int kTS = 64;   // block rows on the split (three-term) side
+constexpr int kTS = 128;  // block rows on the split (three-term) side
 constexpr int kGK = 32;   // K per LDS stage: four 16-byte chunks per row
 
 int split_real_rows_pad(int n) { return (int)round_up(n, kTS); }
@@ -145,26 +145,43 @@ hipError_t launch_split_prep(bool case_a, const SplitPrepArgs& a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// GEMM over one 256 x 64 block of Z: 256 rows of the integer plane (the I
-// side) against 64 rows of each of the three term planes (the S side); for
+// GEMM over one 256 x 128 block of Z: 256 rows of the integer plane (the I
+// side) against 128 rows of each of the three term planes (the S side); for
 // the case-B product the I side runs along the rows of Z, for case A along its
-// columns.  256 threads = 2 x 2 waves, each wave 128 I rows x 32 S rows =
-// 4 MFMA 32 x 32 blocks, each with a hi and a mid/lo accumulator.  Per 16-wide
-// K step a wave reads 4 integer and 3 term fragments for 12 MFMAs.
+// columns.  One block of 8 waves per compute unit (two waves per SIMD, so one
+// wave's MFMAs run while the other waits): wave w owns I rows 128 (w & 1) ..
+// +127 and S rows 32 (w >> 1) .. +31, i.e. 4 MFMA 32 x 32 blocks, each with a
+// hi and a mid/lo accumulator (128 binary32 accumulators per lane).  Per
+// 16-wide K step a wave reads 4 integer and 3 term fragments for 12 MFMAs.
 //
 // MFMA 32x32x16 operand layout: lane l supplies row (l % 32) of A (column
 // (l % 32) of B) and the eight K values 8*(l / 32) .. +7 of the 16; result
 // register v of lane l holds row 8*(v / 4) + 4*(l / 32) + v % 4, column l % 32.
 //
-// LDS: a stage holds the I tile (256 rows) then the three S tiles (64 rows),
-// each row 32 bf16 = four 16-byte chunks with chunk q of row r kept at slot
-// q ^ swz(r).  Fragment reads (32 consecutive rows, one chunk) and staging
-// writes (four rows, all chunks) then touch every bank once per 16 lanes.
-constexpr int kPlaneI = kTI * kGK;               // bf16 per I tile
-constexpr int kPlaneS = kTS * kGK;               // bf16 per S tile
-constexpr int kStage = kPlaneI + 3 * kPlaneS;    // 28 KB
+// LDS: three stages of 32 K (120 KB), each the I tile (256 rows) then the
+// three S tiles (128 rows), each row 32 bf16 = four 16-byte chunks with chunk q
+// of row r kept at slot q ^ swz(r).  Fragment reads (32 consecutive rows, one
+// chunk) touch every bank once per 16 lanes.  Global loads go straight into
+// LDS (buffer loads with an LDS destination, 1 KB = 16 rows per instruction;
+// lane L fills slot L % 4 of row L / 4 of the group, so it fetches the chunk
+// that belongs there), two stages ahead of the MFMAs, with one barrier per
+// stage.
+constexpr int kGemmWaves = 8;
+constexpr int kPlaneI = kTI * kGK;                    // bf16 per I tile
+constexpr int kPlaneS = kTS * kGK;                    // bf16 per S tile
+constexpr int kStage = kPlaneI + 3 * kPlaneS;         // 40 KB
+constexpr int kStages = 3;                            // LDS stages in flight
+constexpr int kGroups = kStage / (16 * kGK);          // 1 KB row groups per stage (40)
+constexpr int kGroupsPerWave = kGroups / kGemmWaves;  // 5
+static_assert(kTI == 2 * 128 && kTS == 4 * 32, "wave grid 2 x 4");
+static_assert(kTI / 16 == 2 * kGemmWaves && kTS / 16 == kGemmWaves, "row groups per wave");
 
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// s_waitcnt immediate: vector memory count <= v (bits 3:0 and 15:14), LDS and
+// scalar memory count not waited for (bits 11:8), export count not waited for
+// (bits 6:4).
+constexpr int wait_vm(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (15 << 8); }
 
 // Tile order: each XCD gets a contiguous run of tiles (xcd_remap), and inside
 // it tiles go S-band-major in groups of kGroupI I tiles so that blocks running
@@ -181,43 +198,66 @@ __device__ __forceinline__ void gemm_tile_coords(int t, int tiles_i, int tiles_s
 }
 
 template <bool CASE_A>
-__global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
+__global__ __launch_bounds__(kGemmWaves * 64, 1) void gemm_bf16x3_kernel(
     int M, int N, const uint16_t* __restrict__ I, const uint16_t* __restrict__ S0,
     const uint16_t* __restrict__ S1, const uint16_t* __restrict__ S2, int64_t ld,
     float* __restrict__ Z, int64_t ldz, int tiles_i, int tiles_s) {
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kStage];
+    __shared__ __attribute__((aligned(1024))) uint16_t lds[kStages * kStage];
 
     int ti, ts;
     gemm_tile_coords(xcd_remap(blockIdx.x, tiles_i * tiles_s), tiles_i, tiles_s, ti, ts);
     const int i0 = ti * kTI, s0 = ts * kTS;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wi = (wave & 1) * 128, wsr = (wave >> 1) * 32;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wi = (wave & 1) * 128, ws = (wave >> 1) * 32;
 
-    // Staging: thread tid moves chunk q0 of rows r0 + 64 j: four rows of the I
-    // tile and one of each S tile.  The byte offset inside a 64-row band is
-    // the same for every load (below 2^32 as ld <= 65536); the band bases are
-    // uniform.
-    const int r0 = tid >> 2, q0 = tid & 3;
-    const uint32_t goff = (uint32_t)((int64_t)r0 * ld + q0 * 8) * 2u;
-    const int64_t band = 64 * ld;  // bf16 per 64 rows
-    const char* gI = reinterpret_cast<const char*>(I + (int64_t)i0 * ld);
-    const char* gS0 = reinterpret_cast<const char*>(S0 + (int64_t)s0 * ld);
-    const char* gS1 = reinterpret_cast<const char*>(S1 + (int64_t)s0 * ld);
-    const char* gS2 = reinterpret_cast<const char*>(S2 + (int64_t)s0 * ld);
-    const int lst = r0 * kGK + ((q0 ^ swz(r0)) * 8);  // swz(r0 + 64 j) == swz(r0)
-#define AFMM_GLD(base, j, k0) \
-    (*reinterpret_cast<const uint4*>((base) + ((j) * band + (k0)) * 2 + goff))
-#define AFMM_GLOAD(g, k0)                                                          \
-    g##0 = AFMM_GLD(gI, 0, k0); g##1 = AFMM_GLD(gI, 1, k0);                         \
-    g##2 = AFMM_GLD(gI, 2, k0); g##3 = AFMM_GLD(gI, 3, k0);                         \
-    g##4 = AFMM_GLD(gS0, 0, k0); g##5 = AFMM_GLD(gS1, 0, k0); g##6 = AFMM_GLD(gS2, 0, k0);
-#define AFMM_LST(dst, plane_off, j, v) \
-    *reinterpret_cast<uint4*>((dst) + (plane_off) + (j) * 64 * kGK + lst) = (v);
-#define AFMM_LSTORE(dst, g)                                                         \
-    AFMM_LST(dst, 0, 0, g##0) AFMM_LST(dst, 0, 1, g##1)                             \
-    AFMM_LST(dst, 0, 2, g##2) AFMM_LST(dst, 0, 3, g##3)                             \
-    AFMM_LST(dst, kPlaneI, 0, g##4) AFMM_LST(dst, kPlaneI + kPlaneS, 0, g##5)        \
-    AFMM_LST(dst, kPlaneI + 2 * kPlaneS, 0, g##6)
+    // Buffer resources over the block's rows of each plane (every plane is
+    // padded to whole block tiles, so these rows exist); one covering nothing
+    // for the loads past the last stage.
+    const uint32_t row_bytes = (uint32_t)(ld * 2);
+    const __amdgpu_buffer_rsrc_t rI = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t*>(I + (int64_t)i0 * ld), (short)0, (int)(kTI * row_bytes), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rS[3] = {
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(S0 + (int64_t)s0 * ld), (short)0,
+                                          (int)(kTS * row_bytes), 0x00020000),
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(S1 + (int64_t)s0 * ld), (short)0,
+                                          (int)(kTS * row_bytes), 0x00020000),
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(S2 + (int64_t)s0 * ld), (short)0,
+                                          (int)(kTS * row_bytes), 0x00020000)};
+    const __amdgpu_buffer_rsrc_t rZero =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(I), (short)0, 0, 0x00020000);
+    const int n_st = (int)(ld / kGK);  // ld is a multiple of 64: an even count >= 2
+
+    // This wave's row groups of a stage, 16 rows of one plane each: j = 0, 1
+    // the I tile's groups 8 j + wave, j = 2, 3, 4 group `wave` of S tile j - 2.
+    // Lane L fetches row 16 group + L / 4, chunk (L % 4) ^ swz(row) (swz
+    // depends on the row modulo 32).
+    uint32_t voff[kGroupsPerWave];
+#pragma unroll
+    for (int j = 0; j < kGroupsPerWave; ++j) {
+        const int grp = (j < 2 ? 8 * j : 0) + wave;
+        const int row = grp * 16 + (lane >> 2);
+        const int chunk = (lane & 3) ^ swz(row);
+        voff[j] = (uint32_t)row * row_bytes + (uint32_t)chunk * 16u;
+    }
+    // Stage st (K 32 st .. +31) into buffer st % kStages.  Past the last stage
+    // the resource covers no bytes: the loads return zeros into a buffer nobody
+    // reads any more, which keeps the loop free of branches.
+    auto issue = [&](int st) {
+        uint16_t* dst = lds + (st % kStages) * kStage;
+        const uint32_t koff = (uint32_t)st * (kGK * 2);
+        const bool live = st < n_st;
+#pragma unroll
+        for (int j = 0; j < kGroupsPerWave; ++j) {
+            const int plane = j < 2 ? -1 : j - 2;
+            const int grp = (j < 2 ? 8 * j : 0) + wave;
+            __amdgpu_buffer_rsrc_t rs = plane < 0 ? rI : rS[plane];
+            if (!live) rs = rZero;
+            uint16_t* gd = dst + (plane < 0 ? 0 : kPlaneI + plane * kPlaneS) + grp * 16 * kGK;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs, (__attribute__((address_space(3))) void*)gd, 16, voff[j], koff, 0, 0);
+        }
+    };
 
     f32x16 acc_hi[4], acc_lo[4];
 #pragma unroll
@@ -235,63 +275,55 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     const int fo1 = fr * kGK + (((fq + 2) ^ swz(fr)) * 8);  // K step 1: chunks 2, 3
 #define AFMM_FRAG(cur, off) (*reinterpret_cast<const bf16x8*>((cur) + (off)))
 #define AFMM_MFMA(acc, a, b) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    // Both 16-wide K steps of the stage in buffer cur: hi into its own set,
-    // lo then mid into the second.
-#define AFMM_COMPUTE(cur)                                                                 \
-    _Pragma("unroll") for (int kk = 0; kk < 2; ++kk) {                                    \
-        const int fo = kk ? fo1 : fo0;                                                    \
-        bf16x8 fi[4], fs[3];                                                              \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i)                                     \
-            fi[i] = AFMM_FRAG(cur, (wi + 32 * i) * kGK + fo);                             \
-        _Pragma("unroll") for (int t = 0; t < 3; ++t)                                     \
-            fs[t] = AFMM_FRAG(cur, kPlaneI + t * kPlaneS + wsr * kGK + fo);               \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
-            if (CASE_A) { AFMM_MFMA(acc_hi[i], fs[0], fi[i]) } else { AFMM_MFMA(acc_hi[i], fi[i], fs[0]) } \
-        }                                                                                 \
-        _Pragma("unroll") for (int t = 2; t >= 1; --t)                                    \
-        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
-            if (CASE_A) { AFMM_MFMA(acc_lo[i], fs[t], fi[i]) } else { AFMM_MFMA(acc_lo[i], fi[i], fs[t]) } \
-        }                                                                                 \
+    // The fragments of one 16-wide K step from the stage at cur, and its MFMAs:
+    // hi into its own set, lo then mid into the second.
+#define AFMM_READ(fi, fs, cur, fo)                                                        \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
+        fi[i] = AFMM_FRAG(cur, (wi + 32 * i) * kGK + (fo));                               \
+    _Pragma("unroll") for (int t = 0; t < 3; ++t)                                         \
+        fs[t] = AFMM_FRAG(cur, kPlaneI + t * kPlaneS + ws * kGK + (fo));
+#define AFMM_STEP(fi, fs)                                                                 \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
+        if (CASE_A) { AFMM_MFMA(acc_hi[i], fs[0], fi[i]) }                                \
+        else { AFMM_MFMA(acc_hi[i], fi[i], fs[0]) }                                       \
+    }                                                                                     \
+    _Pragma("unroll") for (int t = 2; t >= 1; --t)                                        \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
+        if (CASE_A) { AFMM_MFMA(acc_lo[i], fs[t], fi[i]) }                                \
+        else { AFMM_MFMA(acc_lo[i], fi[i], fs[t]) }                                       \
     }
 
-    // Global loads run two stages ahead of the MFMAs through two register
-    // sets: stage s + 2 is loaded into one set while stage s is computed, and
-    // the other set (stage s + 1) is written to the free LDS buffer at the end
-    // of stage s.  ld is a multiple of 64, so the stage count is even and the
-    // loop takes stages in pairs (s in buffer 0, s + 1 in buffer 1).
-    const int n_k = (int)(ld / kGK);
-    uint4 ga0, ga1, ga2, ga3, ga4, ga5, ga6, gb0, gb1, gb2, gb3, gb4, gb5, gb6;
-    uint16_t* const buf0 = lds;
-    uint16_t* const buf1 = lds + kStage;
-    AFMM_GLOAD(ga, 0)
-    AFMM_GLOAD(gb, kGK)
-    AFMM_LSTORE(buf0, ga)
-    __syncthreads();
-    for (int ks = 0; ks < n_k; ks += 2) {
-        if (ks + 2 < n_k) {
-            AFMM_GLOAD(ga, (int64_t)(ks + 2) * kGK)
-        }
-        AFMM_COMPUTE(buf0)
-        AFMM_LSTORE(buf1, gb)
-        __syncthreads();
-        if (ks + 3 < n_k) {
-            AFMM_GLOAD(gb, (int64_t)(ks + 3) * kGK)
-        }
-        AFMM_COMPUTE(buf1)
-        if (ks + 2 < n_k) {
-            AFMM_LSTORE(buf0, ga)
-        }
-        __syncthreads();
+    // Stages st + 1 and st + 2 are in flight while st is computed.  At the top
+    // of each stage a wave waits for its own loads of the stage, then the
+    // barrier: every wave's loads of it have landed, and every wave is done
+    // with the buffer the next issue overwrites.  (A plain barrier: the
+    // compiler's workgroup barrier would also wait for the loads still in
+    // flight for the next stage.)
+    issue(0);
+    issue(1);
+    for (int st = 0; st < n_st; ++st) {
+        __builtin_amdgcn_s_waitcnt(wait_vm(kGroupsPerWave));  // stage st landed
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        const uint16_t* cur = lds + (st % kStages) * kStage;
+        // the compiler spreads the reads between the MFMAs (reading both steps'
+        // fragments at once queues the LDS up behind eight waves: slower)
+        bf16x8 fi0[4], fs0[3], fi1[4], fs1[3];
+        AFMM_READ(fi0, fs0, cur, fo0)
+        issue(st + 2);
+        AFMM_READ(fi1, fs1, cur, fo1)
+        AFMM_STEP(fi0, fs0)
+        AFMM_STEP(fi1, fs1)
     }
+    // the zero loads past the last stage must land before the block's LDS goes
+    __builtin_amdgcn_s_waitcnt(wait_vm(0));
 #undef AFMM_FRAG
 #undef AFMM_MFMA
-#undef AFMM_COMPUTE
-#undef AFMM_GLD
-#undef AFMM_GLOAD
-#undef AFMM_LST
-#undef AFMM_LSTORE
+#undef AFMM_READ
+#undef AFMM_STEP
 
-    // block i covers I rows wi + 32 i .. +31 and S rows wsr .. wsr + 31; the
+    // block i covers I rows wi + 32 i .. +31 and S rows ws .. ws + 31; the
     // MFMA's A operand (its result rows) is the I side for case B and the S
     // side for case A.
 #pragma unroll
@@ -299,8 +331,8 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int a = 8 * (v / 4) + 4 * (lane >> 5) + (v & 3), b = lane & 31;
-            const int row = CASE_A ? s0 + wsr + a : i0 + wi + 32 * i + a;
-            const int col = CASE_A ? i0 + wi + 32 * i + b : s0 + wsr + b;
+            const int row = CASE_A ? s0 + ws + a : i0 + wi + 32 * i + a;
+            const int col = CASE_A ? i0 + wi + 32 * i + b : s0 + ws + b;
             if (row < M && col < N) Z[(int64_t)row * ldz + col] = acc_hi[i][v] + acc_lo[i][v];
         }
 }
@@ -314,10 +346,10 @@ hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, cons
     const int tiles_i = (rows_i + kTI - 1) / kTI, tiles_s = (rows_s + kTS - 1) / kTS;
     const int n_tiles = tiles_i * tiles_s;
     if (case_a)
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(256), 0, s, M, N, I, S0,
+        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(kGemmWaves * 64), 0, s, M, N, I, S0,
                            S1, S2, ld, Z, ldz, tiles_i, tiles_s);
     else
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(256), 0, s, M, N, I, S0,
+        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(kGemmWaves * 64), 0, s, M, N, I, S0,
                            S1, S2, ld, Z, ldz, tiles_i, tiles_s);
     return hipGetLastError();
 }
