@@ -370,9 +370,19 @@ def c5(args):
     strict_launches = max(steps, 5)
     strict_median, strict_min = per_launch_ms(lambda: afmm.multiply("A", Xd, Yd, out=Z),
                                               strict_launches, stream)
-    log(f"bench: c5 strict {strict_ms:.2f} ms (median {strict_median:.2f}, min {strict_min:.2f})")
+    form = afmm.plain_form("A", Xd, Yd)
+    log(f"bench: c5 strict plain call {strict_ms:.2f} ms (median {strict_median:.2f}, "
+        f"min {strict_min:.2f}), form chosen on the device: mapping {form}")
+    # the size-keyed form run explicitly (what the plain call ran before it chose
+    # from the data)
+    size_keyed = afmm.default_config("A", n)
+    Zk = afmm.multiply("A", Xd, Yd, config=size_keyed)
+    keyed_ms = event_time_ms(lambda: afmm.multiply("A", Xd, Yd, out=Zk, config=size_keyed),
+                             steps, stream)
+    log(f"bench: c5 strict size-keyed form {keyed_ms:.2f} ms")
+    del Zk
     # the compacted-base form (lanes over each k's non-zero bases, Z block in LDS),
-    # chosen explicitly: the size-keyed default cannot see the real factor's density
+    # run explicitly
     Zc = afmm.multiply("A", Xd, Yd, config=SPARSE_REAL_CONFIG)
     acc_ms = event_time_ms(lambda: afmm.multiply("A", Xd, Yd, out=Zc, config=SPARSE_REAL_CONFIG),
                            steps, stream)
@@ -399,13 +409,17 @@ def c5(args):
                       "bitexact_sampled_rows": bool(np.array_equal(Zh.view(np.uint32),
                                                                    Zr.view(np.uint32))),
                       "rel_frobenius_err_vs_f64": oracle.rel_frobenius(Zh, Z64),
-                      "kernel_config": list(afmm.default_config("A", n))},
+                      "form_chosen_on_device": form,
+                      "vs_best_explicit_form": strict_ms / min(keyed_ms, acc_ms)},
+           "strict_size_keyed": {"ms": keyed_ms, "kernel_config": list(size_keyed),
+                                 "frac_of_add_peak": adds / (keyed_ms * 1e-3) / 1e12
+                                 / PEAK_ADD_TFLOPS},
            "strict_compacted_base": {
                "ms": acc_ms, "useful_adds_per_s": adds / (acc_ms * 1e-3),
                "frac_of_add_peak": adds / (acc_ms * 1e-3) / 1e12 / PEAK_ADD_TFLOPS,
                "bitexact_sampled_rows": bool(np.array_equal(Zch.view(np.uint32),
                                                             Zr.view(np.uint32))),
-               "speedup_over_default_strict": strict_ms / acc_ms,
+               "speedup_over_size_keyed": keyed_ms / acc_ms,
                "kernel_config": list(SPARSE_REAL_CONFIG)},
            "split": {"ms": split_ms, "effective_2n3_per_s": 2.0 * n ** 3 / (split_ms * 1e-3),
                      "mfma_frac_of_bf16_peak": 6.0 * n ** 3 / (split_ms * 1e-3) / 1e12
@@ -620,7 +634,7 @@ def main():
         "data": "synthetic (seeded generator)",
         "config": {"workload": w.name, "case": "B", "n": n, "d1": 0.3, "d2": 0.9,
                    "int_dist": "Poisson(3) clipped to [0,255]", "real_dist": "N(0,1)",
-                   "kernel_config": list(cfg)},
+                   "kernel_config": list(cfg), "form_chosen_on_device": afmm.plain_form("B", Xd, Yd)},
         "useful_adds": adds,
         "strict": {"ms": strict_ms, "ms_median": strict_median, "ms_min": strict_min,
                    "launches_timed_one_by_one": strict_launches,

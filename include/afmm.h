@@ -86,7 +86,11 @@ typedef enum {
  * Bytes of device scratch a multiply of this case, size and mode needs.
  * Pass at least that much as `workspace` to the multiply calls, or pass
  * workspace = NULL to let the library take it from the stream-ordered HIP
- * allocator (hipMallocAsync / hipFreeAsync on `stream`).
+ * allocator (hipMallocAsync / hipFreeAsync on `stream`).  For a strict
+ * product that chooses its form on the device (see afmm_multiply_caseA) this
+ * covers every form it may choose: about 17 n^2 bytes (case B) or 21 n^2
+ * (case A), against n^2 (B) or 5 n^2 (A) for the size-keyed form alone
+ * (afmm_workspace_size_config of afmm_default_config).
  */
 size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode);
 
@@ -94,6 +98,14 @@ size_t afmm_workspace_size(afmm_case c, int64_t n, afmm_mode mode);
  * Case A product (Section 2, Case-A loop).  X: n x n binary32, Y: n x n
  * int32 (repetition counts), Z: n x n binary32 output.  See the mode notes
  * above.  workspace / workspace_bytes: caller scratch or NULL / 0.
+ *
+ * Strict mode picks its kernel form on the device, with no wait for the host,
+ * when 1024 <= n <= 16384 and the size-keyed configuration (afmm_default_config)
+ * is a dense one (mapping 0, 2 or 3): two small kernels count the participating
+ * entries of 128 evenly spaced rows of each factor and apply the rule of
+ * afmm_suggest_config to these sampled densities, and the kernels of the forms
+ * not chosen return at once.  Every form gives the same bits, so the choice
+ * changes only the time.  afmm_plain_form reports the choice.
  */
 afmm_status afmm_multiply_caseA(int64_t n, const float *X, const int32_t *Y, float *Z,
                                 afmm_mode mode, void *workspace, size_t workspace_bytes,
@@ -254,6 +266,17 @@ size_t afmm_workspace_size_config(afmm_case c, int64_t n, const afmm_config *cfg
 afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void *X, const void *Y,
                                 hipStream_t stream, afmm_config *out);
 
+/*
+ * The mapping (afmm_config.mapping) a strict afmm_multiply_caseA / caseB call
+ * on these operands runs, chosen exactly as that call chooses it (see
+ * afmm_multiply_caseA): written as one int32 to *d_mapping (device) on
+ * `stream`, asynchronously.  workspace: 4096 bytes or NULL.  A diagnostic for
+ * callers that want to see which form their data gets.
+ */
+afmm_status afmm_plain_form(afmm_case c, int64_t n, const void *X, const void *Y,
+                            int32_t *d_mapping, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
 /* Strict product with an explicit configuration (for the autotuner). */
 afmm_status afmm_multiply_strict_config(afmm_case c, int64_t n, const void *X, const void *Y,
                                         float *Z, const afmm_config *cfg, void *workspace,
@@ -333,10 +356,11 @@ afmm_status afmm_multiply_batched(const afmm_problem *problems, int32_t count, a
  * that the library keeps on every device it runs on, for the life of the
  * process.  The call performs no allocation.  X, Y, Z and their layout are as
  * for the square calls (case A: X binary32, Y int32; case B the other way).
- * Returns AFMM_ERR_WORKSPACE when the product's workspace
- * (afmm_workspace_size(c, n, AFMM_MODE_STRICT)) exceeds the array; with the
- * built-in configurations that admits case B up to n = 9984 and case A up to
- * n = 4480.  All calls on one device share its array and every call rewrites
+ * The call runs the size-keyed form
+ * (afmm_default_config; it does not choose a form from the data) and returns
+ * AFMM_ERR_WORKSPACE when that form's workspace (afmm_workspace_size_config)
+ * exceeds the array; with the built-in configurations that admits case B up
+ * to n = 9984 and case A up to n = 4480.  All calls on one device share its array and every call rewrites
  * what it uses: calls that overlap in time on one device (different streams,
  * or host threads racing) race on it and are not allowed.
  */

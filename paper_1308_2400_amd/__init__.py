@@ -68,6 +68,7 @@ _SIGS = {
     "afmm_default_config": ([_ci, _i64], afmm_config),
     "afmm_workspace_size_config": ([_ci, _i64, ctypes.POINTER(afmm_config)], _sz),
     "afmm_suggest_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config)], _ci),
+    "afmm_plain_form": ([_ci, _i64, _vp, _vp, _vp, _vp, _sz, _vp], _ci),
     "afmm_multiply_strict_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config), _vp,
                                      _sz, _vp], _ci),
     "afmm_set_tuning": ([_i32, _vp, _vp, _vp, _vp], _ci),
@@ -275,6 +276,19 @@ def suggest_config(case, X, Y):
     _check("suggest_config", _lib.afmm_suggest_config(c, n, X.data_ptr(), Y.data_ptr(), _stream(),
                                                       ctypes.byref(out)))
     return out.as_tuple()
+
+
+def plain_form(case, X, Y) -> int:
+    """Mapping a plain strict multiply of (X, Y) runs, as that call chooses it on
+    the device (synchronises to read it back)."""
+    torch = _torch()
+    c, m, k, n, ldx, ldy = _shape(case, X, Y)
+    if not _square(m, k, n, ldx, ldy):
+        raise ValueError("plain_form takes square contiguous operands")
+    out = torch.empty(1, dtype=torch.int32, device=X.device)
+    _check("plain_form", _lib.afmm_plain_form(c, n, X.data_ptr(), Y.data_ptr(), out.data_ptr(),
+                                              None, 0, _stream()))
+    return int(out.item())
 
 
 def _cfg(cfg):

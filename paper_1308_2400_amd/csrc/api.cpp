@@ -218,25 +218,14 @@ afmm_config builtin_config(afmm_case c, int64_t n) {
     return lds_config(n);
 }
 
-afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
-                       const afmm_config& cfg, void* ws, size_t ws_bytes, hipStream_t s) {
-    const StrictLayout L = strict_layout(c, p, cfg);
-    Scratch sc;
-    const afmm_status st = sc.get(ws, ws_bytes, L.total, s);
-    if (st != AFMM_OK) return st;
-    if (cfg.mapping == 7) {
-        const int cid = c == AFMM_CASE_A ? 0 : 1;
-        const RowsLists lists =
-            rows_lists_at(sc.at(0), (int)p.m, (int)p.k, (int)p.n, cfg.cols_per_lane);
-        AFMM_HIP(launch_compact_rows(cid, X, p.ldx, Y, p.ldy, (int)p.m, (int)p.k, (int)p.n,
-                                     cfg.cols_per_lane, lists, s));
-        AFMM_HIP(launch_rep_rows(cid, (int)p.m, (int)p.k, (int)p.n, lists, Z, p.ldz,
-                                 cfg.cols_per_lane, cfg.waves, s));
-        return AFMM_OK;
-    }
-    uint8_t* P8 = sc.at(L.p8);
-    uint32_t* esc = reinterpret_cast<uint32_t*>(sc.at(L.esc));
-    StrictArgs a{};
+// Count bytes (and case A's transposed real factor) into the workspace at
+// base, laid out by L, and the kernel arguments over them.  gate: see AFMM_GATE.
+afmm_status strict_prepare(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
+                           const StrictLayout& L, uint8_t* base, const uint32_t* gate,
+                           StrictArgs& a, hipStream_t s) {
+    uint8_t* P8 = base + L.p8;
+    uint32_t* esc = reinterpret_cast<uint32_t*>(base + L.esc);
+    a = StrictArgs{};
     a.n_k = (int)p.k;
     a.P8 = P8;
     a.ldp = L.ldp;
@@ -245,7 +234,7 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
     if (c == AFMM_CASE_B) {
         // rows i carry the counts X[i,k]; lanes over j read Y[k,j]
         AFMM_HIP(launch_pack_rows(static_cast<const int32_t*>(X), (int)p.m, (int)p.k, p.ldx, P8,
-                                  L.ldp, L.rows_pad, esc, s));
+                                  L.ldp, L.rows_pad, esc, s, gate));
         a.n_r = (int)p.m;
         a.n_c = (int)p.n;
         a.P32 = static_cast<const int32_t*>(X);
@@ -259,11 +248,11 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
         a.q_padded = false;
     } else {
         // transposed problem: rows j carry the counts Y[k,j]; lanes over i read X[i,k]
-        float* Xt = reinterpret_cast<float*>(sc.at(L.xt));
+        float* Xt = reinterpret_cast<float*>(base + L.xt);
         AFMM_HIP(launch_pack_transpose(static_cast<const int32_t*>(Y), (int)p.k, (int)p.n, p.ldy,
-                                       P8, L.ldp, L.rows_pad, esc, s));
+                                       P8, L.ldp, L.rows_pad, esc, s, gate));
         AFMM_HIP(launch_transpose_f32(static_cast<const float*>(X), (int)p.m, (int)p.k, p.ldx, Xt,
-                                      L.ldq, (int)round_up(p.k, kKPad), s));
+                                      L.ldq, (int)round_up(p.k, kKPad), s, gate));
         a.n_r = (int)p.n;
         a.n_c = (int)p.m;
         a.P32 = static_cast<const int32_t*>(Y);
@@ -276,10 +265,17 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
         a.trans_out = true;
         a.q_padded = true;
     }
+    return AFMM_OK;
+}
+
+// The kernels of a count-uniform configuration (mappings 0, 2, 3, 4) over the
+// prepared arguments; lists: the compacted-base lists (mapping 4).
+afmm_status strict_launch(const afmm_config& cfg, const Shape& p, const StrictArgs& a,
+                          uint8_t* lists, hipStream_t s) {
     if (cfg.mapping == 4 && rep_acc_usable(a, cfg.cols_per_lane)) {
-        const AccLists lists = acc_lists_at(sc.at(L.acc), a.n_c, a.n_k, cfg.cols_per_lane);
-        AFMM_HIP(launch_compact_base(a.Q, a.ldq, a.n_k, a.n_c, cfg.cols_per_lane, lists, s));
-        AFMM_HIP(launch_rep_acc(a, lists, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves,
+        const AccLists L = acc_lists_at(lists, a.n_c, a.n_k, cfg.cols_per_lane);
+        AFMM_HIP(launch_compact_base(a.Q, a.ldq, a.n_k, a.n_c, cfg.cols_per_lane, L, s, a.gate));
+        AFMM_HIP(launch_rep_acc(a, L, cfg.rows_per_wave, cfg.cols_per_lane, cfg.waves,
                                 cfg.unroll == 0 ? 1 : cfg.unroll,
                                 cfg.k_panel == 0 ? 16 : cfg.k_panel, s));
     } else if (cfg.mapping == 2 && rep_direct_usable(a)) {
@@ -302,6 +298,143 @@ afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y
     return AFMM_OK;
 }
 
+// The row-list form (mapping 7): lists of both factors at base, then the kernel.
+afmm_status rows_launch(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
+                        const afmm_config& cfg, uint8_t* base, const uint32_t* gate,
+                        hipStream_t s) {
+    const int cid = c == AFMM_CASE_A ? 0 : 1;
+    const RowsLists lists = rows_lists_at(base, (int)p.m, (int)p.k, (int)p.n, cfg.cols_per_lane);
+    AFMM_HIP(launch_compact_rows(cid, X, p.ldx, Y, p.ldy, (int)p.m, (int)p.k, (int)p.n,
+                                 cfg.cols_per_lane, lists, s, gate));
+    AFMM_HIP(launch_rep_rows(cid, (int)p.m, (int)p.k, (int)p.n, lists, Z, p.ldz,
+                             cfg.cols_per_lane, cfg.waves, s, gate));
+    return AFMM_OK;
+}
+
+afmm_status strict_run(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
+                       const afmm_config& cfg, void* ws, size_t ws_bytes, hipStream_t s) {
+    const StrictLayout L = strict_layout(c, p, cfg);
+    Scratch sc;
+    afmm_status st = sc.get(ws, ws_bytes, L.total, s);
+    if (st != AFMM_OK) return st;
+    if (cfg.mapping == 7) return rows_launch(c, p, X, Y, Z, cfg, sc.at(0), nullptr, s);
+    StrictArgs a;
+    if ((st = strict_prepare(c, p, X, Y, Z, L, sc.at(0), nullptr, a, s)) != AFMM_OK) return st;
+    return strict_launch(cfg, p, a, sc.at(L.acc), s);
+}
+
+// ---- the plain strict call's choice of form, made on the device -------------
+// Below this size the size-keyed configuration is right for any density.
+constexpr int64_t kAdaptMin = 1024;
+
+// The two forms for sparse factors the plain call may choose instead of the
+// size-keyed one (what afmm_suggest_config returns).
+afmm_config sparse_real_config(int64_t size) {
+    return size <= 2896 ? afmm_config{4, 1, 64, 8, 2, 8} : afmm_config{4, 2, 32, 8, 2, 8};
+}
+afmm_config row_list_config(int64_t size) {
+    return afmm_config{7, 1, size <= 2896 ? 16 : 32, 16, 1, 16};
+}
+// d_real * d_int * size at or below which the row-list form wins
+double row_list_threshold(afmm_case c) { return c == AFMM_CASE_A ? 32.0 : 42.0; }
+constexpr double kSparseRealMax = 0.06;  // d_real at or below which the compacted base wins
+
+// Above this size the lists of the two sparse forms (up to 24 bytes per entry
+// of a factor) would cost more memory than the choice is worth.
+constexpr int64_t kAdaptMax = 16384;
+
+bool adaptive(afmm_case c, const Shape& p, const afmm_config& d) {
+    (void)c;
+    const int64_t size = shape_size(p);
+    return size >= kAdaptMin && size <= kAdaptMax &&
+           std::max({p.m, p.k, p.n}) <= kAdaptMax &&
+           (d.mapping == 0 || d.mapping == 2 || d.mapping == 3);
+}
+
+// Workspace of the adaptive strict call: the choice's control words, then the
+// count bytes and transposed factor of the count-uniform forms, then one region
+// holding either form's lists (only the chosen form writes there).
+struct AdaptiveLayout {
+    StrictLayout L;  // offsets relative to base = workspace + kCtlBytes
+    size_t lists, total;
+};
+constexpr size_t kCtlBytes = (kChooseCtlBytes + 255) / 256 * 256;
+static_assert(kCtlBytes <= 4096, "afmm_plain_form documents 4096 bytes of workspace");
+
+AdaptiveLayout adaptive_layout(afmm_case c, const Shape& p) {
+    AdaptiveLayout A;
+    const int64_t size = shape_size(p);
+    const afmm_config c4 = sparse_real_config(size), c7 = row_list_config(size);
+    A.L = strict_layout(c, p, c4);
+    const size_t acc = acc_lists_bytes((int)(c == AFMM_CASE_B ? p.n : p.m), (int)p.k,
+                                       c4.cols_per_lane);
+    const size_t rows = rows_lists_bytes((int)p.m, (int)p.k, (int)p.n, c7.cols_per_lane);
+    A.lists = A.L.acc;
+    A.total = kCtlBytes + A.L.acc + std::max(acc, rows);
+    return A;
+}
+
+// Launches the choice of form over the control words at ctl (kChooseCtlBytes).
+// adapt false: the choice is the size-keyed form whatever the density.
+hipError_t choose_form(afmm_case c, const Shape& p, const void* X, const void* Y,
+                       const afmm_config& d, bool adapt, uint8_t* ctl, int32_t* chosen,
+                       hipStream_t s) {
+    const int64_t size = shape_size(p);
+    const bool case_a = c == AFMM_CASE_A;
+    // the real factor: X (m x k) in case A, Y (k x n) in case B; the counts the other
+    ChooseArgs ch;
+    ch.R = case_a ? X : Y;
+    ch.r_rows = (int)(case_a ? p.m : p.k);
+    ch.r_cols = (int)(case_a ? p.k : p.n);
+    ch.ldr = case_a ? p.ldx : p.ldy;
+    ch.I = case_a ? Y : X;
+    ch.i_rows = (int)(case_a ? p.k : p.m);
+    ch.i_cols = (int)(case_a ? p.n : p.k);
+    ch.ldi = case_a ? p.ldy : p.ldx;
+    ch.size = (double)size;
+    ch.row_list_max = row_list_threshold(c);
+    ch.sparse_real_max = kSparseRealMax;
+    // the compacted-base form needs 31-bit offsets over its lists and count bytes
+    StrictArgs probe{};
+    probe.n_r = (int)(case_a ? p.n : p.m);
+    probe.n_c = (int)(case_a ? p.m : p.n);
+    probe.n_k = (int)p.k;
+    probe.ldp = round_up(p.k, kKPad);
+    ch.allow_sparse_real = rep_acc_usable(probe, sparse_real_config(size).cols_per_lane) ? 1 : 0;
+    if (!adapt) {
+        ch.row_list_max = -1.0;
+        ch.allow_sparse_real = 0;
+    }
+    ch.default_mapping = d.mapping;
+    ch.chosen = chosen;
+    return launch_choose_form(ch, ctl, s);
+}
+
+afmm_status strict_adaptive(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
+                            const afmm_config& d, void* ws, size_t ws_bytes, hipStream_t s) {
+    const int64_t size = shape_size(p);
+    const afmm_config c4 = sparse_real_config(size), c7 = row_list_config(size);
+    const AdaptiveLayout A = adaptive_layout(c, p);
+    Scratch sc;
+    afmm_status st = sc.get(ws, ws_bytes, A.total, s);
+    if (st != AFMM_OK) return st;
+    uint8_t* ctl = sc.at(0);
+    uint8_t* base = sc.at(kCtlBytes);
+    AFMM_HIP(choose_form(c, p, X, Y, d, true, ctl, nullptr, s));
+    const uint32_t* gates = choose_gates(ctl);
+    const uint32_t* g_default = gates + 0;  // the size-keyed form's kernels
+    const uint32_t* g_counts = gates + 1;   // count bytes (either count-uniform form)
+    const uint32_t* g_sparse_real = gates + 2;
+    const uint32_t* g_row_list = gates + 3;
+    StrictArgs a;
+    if ((st = strict_prepare(c, p, X, Y, Z, A.L, base, g_counts, a, s)) != AFMM_OK) return st;
+    a.gate = g_default;
+    if ((st = strict_launch(d, p, a, base + A.lists, s)) != AFMM_OK) return st;
+    a.gate = g_sparse_real;
+    if ((st = strict_launch(c4, p, a, base + A.lists, s)) != AFMM_OK) return st;
+    return rows_launch(c, p, X, Y, Z, c7, base + A.lists, g_row_list, s);
+}
+
 SplitLayout split_layout(afmm_case c, const Shape& p) {
     return split_planes_layout(c == AFMM_CASE_A, (int)p.m, (int)p.k, (int)p.n);
 }
@@ -322,7 +455,9 @@ afmm_status split_run(afmm_case c, const Shape& p, const void* X, const void* Y,
 size_t workspace_for(afmm_case c, const Shape& p, afmm_mode mode) {
     if (mode == AFMM_MODE_SPLIT_BF16X3) return split_layout(c, p).total;
     const afmm_config cfg = afmm_default_config(c, shape_size(p));
-    return std::max(strict_layout(c, p, cfg).total, count_ws(p));
+    const size_t strict = adaptive(c, p, cfg) ? adaptive_layout(c, p).total
+                                              : strict_layout(c, p, cfg).total;
+    return std::max(strict, count_ws(p));
 }
 
 afmm_status multiply(afmm_case c, const Shape& p, const void* X, const void* Y, float* Z,
@@ -331,8 +466,11 @@ afmm_status multiply(afmm_case c, const Shape& p, const void* X, const void* Y, 
     if (st != AFMM_OK) return st;
     if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;
     if ((st = check_device()) != AFMM_OK) return st;
-    if (mode == AFMM_MODE_STRICT)
-        return strict_run(c, p, X, Y, Z, afmm_default_config(c, shape_size(p)), ws, ws_bytes, s);
+    if (mode == AFMM_MODE_STRICT) {
+        const afmm_config d = afmm_default_config(c, shape_size(p));
+        if (adaptive(c, p, d)) return strict_adaptive(c, p, X, Y, Z, d, ws, ws_bytes, s);
+        return strict_run(c, p, X, Y, Z, d, ws, ws_bytes, s);
+    }
     return split_run(c, p, X, Y, Z, ws, ws_bytes, s);
 }
 
@@ -498,7 +636,7 @@ afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void* X, const voi
     afmm_status st = check_device();
     if (st != AFMM_OK) return st;
     *out = afmm_default_config(c, n);
-    if (n < 1024) return AFMM_OK;  // below this the size-keyed choice holds for any density
+    if (n < kAdaptMin) return AFMM_OK;  // below this the size-keyed choice holds for any density
     void* buf = nullptr;
     hipError_t e = hipMallocAsync(&buf, 16, stream);
     if (e != hipSuccess) return hip_fail(e);
@@ -520,10 +658,26 @@ afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void* X, const voi
     // k of a row, is at most 32 in case A, where a lane loops its own count, and
     // 42 in case B), the compacted-base form when the real factor alone is very
     // sparse, the size-keyed choice otherwise
-    if (d_real * d_int * (double)n <= (c == AFMM_CASE_A ? 32.0 : 42.0))
-        *out = afmm_config{7, 1, n <= 2896 ? 16 : 32, 16, 1, 16};
-    else if (d_real <= 0.06)
-        *out = n <= 2896 ? afmm_config{4, 1, 64, 8, 2, 8} : afmm_config{4, 2, 32, 8, 2, 8};
+    if (d_real * d_int * (double)n <= row_list_threshold(c))
+        *out = row_list_config(n);
+    else if (d_real <= kSparseRealMax)
+        *out = sparse_real_config(n);
+    return AFMM_OK;
+}
+
+afmm_status afmm_plain_form(afmm_case c, int64_t n, const void* X, const void* Y,
+                            int32_t* d_mapping, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+    if (n < 1 || n > AFMM_MAX_N || !X || !Y || !d_mapping ||
+        (c != AFMM_CASE_A && c != AFMM_CASE_B))
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    const Shape p = square(n);
+    const afmm_config d = afmm_default_config(c, n);
+    Scratch sc;
+    if ((st = sc.get(workspace, workspace_bytes, kCtlBytes, stream)) != AFMM_OK) return st;
+    AFMM_HIP(choose_form(c, p, X, Y, d, adaptive(c, p, d), sc.at(0), d_mapping, stream));
     return AFMM_OK;
 }
 

@@ -22,6 +22,13 @@ __device__ __forceinline__ int xcd_remap(int bid, int n_tiles) {
     return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// A launch queued for a choice made on the device: the kernel leaves at once
+// unless its gate word is non-zero (a null gate: it always runs).
+#define AFMM_GATE(g)                           \
+    do {                                       \
+        if ((g) != nullptr && *(g) == 0u) return; \
+    } while (0)
+
 // Saturating byte of a repetition count: <= 0 -> 0 (no additions), 1..254 as
 // is, >= 255 -> 255, which tells the kernel to re-read the full int32 count.
 __device__ __forceinline__ uint32_t count_byte(int32_t v) {
@@ -62,12 +69,16 @@ void set_last_hip_error(int e);
 // prep.hip
 // Both clear *esc first and set it when some count byte is 255.
 // I / X: rows x cols with leading dimension ldi / ldx.
+// gate: see AFMM_GATE (nullable).
 hipError_t launch_pack_rows(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
-                            int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s);
+                            int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s,
+                            const uint32_t* gate = nullptr);
 hipError_t launch_pack_transpose(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
-                                 int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s);
+                                 int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s,
+                                 const uint32_t* gate = nullptr);
 hipError_t launch_transpose_f32(const float* X, int rows, int cols, int64_t ldx, float* Xt,
-                                int64_t ldq, int rows_pad, hipStream_t s);
+                                int64_t ldq, int rows_pad, hipStream_t s,
+                                const uint32_t* gate = nullptr);
 // X: m x kd (ldx), Y: kd x n (ldy); wk: kd entries, rows: m entries.
 hipError_t launch_count(int case_id, int m, int kd, int n, const void* X, int64_t ldx,
                         const void* Y, int64_t ldy, uint64_t* wk, uint64_t* rows, uint64_t* total,
@@ -83,6 +94,7 @@ struct StrictArgs {
     const uint32_t* esc;                     // device word: non-zero if a byte is 255
     bool trans_out;                          // z_sr == 1: output (r, c) at c*z_sc + r
     bool q_padded;                           // Q rows readable up to round_up(n_c, 4)
+    const uint32_t* gate = nullptr;          // see AFMM_GATE
 };
 hipError_t launch_rep_uniform(const StrictArgs& a, int R, int C, int W, int U, int KP,
                               hipStream_t s);

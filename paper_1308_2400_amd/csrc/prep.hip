@@ -19,7 +19,9 @@ __global__ void zero_u32_kernel(uint32_t* w) { *w = 0; }
 __global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restrict__ I, int rows,
                                                        int cols, int64_t ldi,
                                                        uint8_t* __restrict__ P8, int64_t ldp,
-                                                       int rows_pad, uint32_t* __restrict__ esc) {
+                                                       int rows_pad, uint32_t* __restrict__ esc,
+                                                       const uint32_t* __restrict__ gate) {
+    AFMM_GATE(gate);
     bool hit = false;
     const int64_t words_per_row = ldp / 4;
     const int64_t total = (int64_t)rows_pad * words_per_row;
@@ -48,7 +50,9 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(const int32_t* __restric
 __global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __restrict__ I, int rows,
                                                             int cols, int64_t ldi,
                                                             uint8_t* __restrict__ P8,
-                                                            int64_t ldp, uint32_t* __restrict__ esc) {
+                                                            int64_t ldp, uint32_t* __restrict__ esc,
+                                                            const uint32_t* __restrict__ gate) {
+    AFMM_GATE(gate);
     __shared__ uint8_t tile[64][64 + 4];
     bool hit = false;
     const int j0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
@@ -76,7 +80,9 @@ __global__ __launch_bounds__(256) void pack_transpose_kernel(const int32_t* __re
 // Block (64, 4).
 __global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restrict__ X, int rows,
                                                            int cols, int64_t ldx,
-                                                           float* __restrict__ Xt, int64_t ldq) {
+                                                           float* __restrict__ Xt, int64_t ldq,
+                                                           const uint32_t* __restrict__ gate) {
+    AFMM_GATE(gate);
     __shared__ float tile[64][64 + 1];
     const int i0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -89,30 +95,33 @@ __global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restr
 }
 
 hipError_t launch_pack_rows(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
-                            int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s) {
+                            int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s,
+                            const uint32_t* gate) {
     const int64_t words = (int64_t)rows_pad * (ldp / 4);
     const int grid = (int)std::min<int64_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
     hipLaunchKernelGGL(pack_rows_kernel, dim3(grid), dim3(256), 0, s, I, rows, cols, ldi, P8, ldp,
-                       rows_pad, esc);
+                       rows_pad, esc, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_transpose(const int32_t* I, int rows, int cols, int64_t ldi, uint8_t* P8,
-                                 int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s) {
+                                 int64_t ldp, int rows_pad, uint32_t* esc, hipStream_t s,
+                                 const uint32_t* gate) {
     // P8 has rows_pad rows (j, from I's columns) and ldp columns (k, from I's rows)
     dim3 grid(rows_pad / 64, (unsigned)(ldp / 64));
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, esc);
     hipLaunchKernelGGL(pack_transpose_kernel, grid, dim3(64, 4), 0, s, I, rows, cols, ldi, P8, ldp,
-                       esc);
+                       esc, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_transpose_f32(const float* X, int rows, int cols, int64_t ldx, float* Xt,
-                                int64_t ldq, int rows_pad, hipStream_t s) {
+                                int64_t ldq, int rows_pad, hipStream_t s, const uint32_t* gate) {
     // Xt has rows_pad rows (k) and ldq columns (i); both multiples of 64.
     dim3 grid((unsigned)(ldq / 64), rows_pad / 64);
-    hipLaunchKernelGGL(transpose_f32_kernel, grid, dim3(64, 4), 0, s, X, rows, cols, ldx, Xt, ldq);
+    hipLaunchKernelGGL(transpose_f32_kernel, grid, dim3(64, 4), 0, s, X, rows, cols, ldx, Xt, ldq,
+                       gate);
     return hipGetLastError();
 }
 

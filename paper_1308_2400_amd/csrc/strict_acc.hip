@@ -40,7 +40,9 @@ __global__ __launch_bounds__(256) void compact_base_kernel(const float* __restri
                                                            int64_t ldq, int n_k, int n_c, int ct,
                                                            int64_t n_k_pad, int64_t n_segs,
                                                            uint2* __restrict__ ent,
-                                                           int32_t* __restrict__ lens) {
+                                                           int32_t* __restrict__ lens,
+                                                           const uint32_t* __restrict__ gate) {
+    AFMM_GATE(gate);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (seg >= n_segs) return;  // whole waves
@@ -68,13 +70,13 @@ __global__ __launch_bounds__(256) void compact_base_kernel(const float* __restri
 }
 
 hipError_t launch_compact_base(const float* Q, int64_t ldq, int n_k, int n_c, int C,
-                               const AccLists& L, hipStream_t s) {
+                               const AccLists& L, hipStream_t s, const uint32_t* gate) {
     const int ct = kWave * C;
     const int64_t bands = (n_c + ct - 1) / ct;
     const int64_t n_segs = bands * L.n_k_pad;
     const int64_t blocks = (n_segs + 3) / 4;
     hipLaunchKernelGGL(compact_base_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Q, ldq, n_k,
-                       n_c, ct, L.n_k_pad, n_segs, L.ent, L.lens);
+                       n_c, ct, L.n_k_pad, n_segs, L.ent, L.lens, gate);
     return hipGetLastError();
 }
 
@@ -311,9 +313,11 @@ __global__ __launch_bounds__(W * kWave) void rep_acc_kernel(
     int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
     const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk, const uint2* __restrict__ ent,
     const int32_t* __restrict__ lens, int64_t n_k_pad, float* __restrict__ Z, int64_t z_sr,
-    int64_t z_sc, const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles) {
+    int64_t z_sc, const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles,
+    const uint32_t* __restrict__ gate) {
     using T = AccTile<R, C, W, KP>;
     __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    AFMM_GATE(gate);
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     if (*esc)
@@ -336,11 +340,11 @@ hipError_t launch_acc(const StrictArgs& a, const AccLists& L, hipStream_t s) {
     if (a.trans_out)
         hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, KP, true>), grid, block, 0, s, a.n_r,
                            a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
-                           L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles);
+                           L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     else
         hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, KP, false>), grid, block, 0, s, a.n_r,
                            a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
-                           L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles);
+                           L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     return hipGetLastError();
 }
 

@@ -16,8 +16,9 @@ struct AccLists {
 size_t acc_lists_bytes(int n_c, int n_k, int C);  // both arrays, each 256-byte aligned
 AccLists acc_lists_at(uint8_t* p, int n_c, int n_k, int C);
 
+// gate: see AFMM_GATE (nullable).
 hipError_t launch_compact_base(const float* Q, int64_t ldq, int n_k, int n_c, int C,
-                               const AccLists& L, hipStream_t s);
+                               const AccLists& L, hipStream_t s, const uint32_t* gate = nullptr);
 hipError_t launch_rep_acc(const StrictArgs& a, const AccLists& L, int R, int C, int W, int U,
                           int KP, hipStream_t s);
 bool rep_acc_supported(int R, int C, int W, int U, int KP);

@@ -13,9 +13,11 @@ __global__ __launch_bounds__(W * kWave) void rep_uniform_kernel(
     int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
     const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
     const float* __restrict__ Q, int64_t ldq, float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
-    const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles) {
+    const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles,
+    const uint32_t* __restrict__ gate) {
     using T = RepTile<R, C, W, KP>;
     __shared__ float lds[T::LDS_FLOATS];
+    AFMM_GATE(gate);
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     if (*esc)
@@ -43,7 +45,7 @@ inline hipError_t launch_rep(const StrictArgs& a, hipStream_t s) {
 #define AFMM_LAUNCH(VEC, TR, BUF)                                                              \
     hipLaunchKernelGGL((rep_uniform_kernel<R, C, W, U, KP, VEC, TR, BUF>), grid, block, 0, s, a.n_r, \
                        a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z,    \
-                       a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles)
+                       a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate)
     if (trans) {
         if (!vec) return hipErrorInvalidValue;  // case A's base is always the padded transpose
         if (buf) AFMM_LAUNCH(true, true, true);
@@ -68,8 +70,10 @@ __global__ __launch_bounds__(W * kWave) void rep_direct_kernel(
     int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
     const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
     const float* __restrict__ Q, int64_t ldq, float* __restrict__ Z, int64_t z_sr, int64_t z_sc,
-    const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles) {
+    const uint32_t* __restrict__ esc, int n_row_blocks, int n_tiles,
+    const uint32_t* __restrict__ gate) {
     constexpr int TM = W * R, TN = kWave * C;
+    AFMM_GATE(gate);
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     if (*esc)
@@ -95,11 +99,11 @@ inline hipError_t launch_direct(const StrictArgs& a, hipStream_t s) {
     if (a.trans_out)
         hipLaunchKernelGGL((rep_direct_kernel<R, C, W, true>), grid, block, 0, s, a.n_r, a.n_c,
                            a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z, a.z_sr,
-                           a.z_sc, a.esc, n_row_blocks, n_tiles);
+                           a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     else
         hipLaunchKernelGGL((rep_direct_kernel<R, C, W, false>), grid, block, 0, s, a.n_r, a.n_c,
                            a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z, a.z_sr,
-                           a.z_sc, a.esc, n_row_blocks, n_tiles);
+                           a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     return hipGetLastError();
 }
 

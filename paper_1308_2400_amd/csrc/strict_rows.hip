@@ -49,7 +49,9 @@ template <bool INT>
 __global__ __launch_bounds__(256) void compact_rows_kernel(const uint32_t* __restrict__ M,
                                                            int64_t ld, int rows, int cols, int ct,
                                                            int64_t n_segs, uint2* __restrict__ ent,
-                                                           int32_t* __restrict__ lens) {
+                                                           int32_t* __restrict__ lens,
+                                                           const uint32_t* __restrict__ gate) {
+    AFMM_GATE(gate);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (seg >= n_segs) return;  // whole waves
@@ -86,24 +88,25 @@ __global__ __launch_bounds__(256) void compact_rows_kernel(const uint32_t* __res
 
 template <bool INT>
 hipError_t launch_compact(const void* M, int64_t ld, int rows, int cols, int ct, uint2* ent,
-                          int32_t* lens, hipStream_t s) {
+                          int32_t* lens, hipStream_t s, const uint32_t* gate) {
     const int64_t bands = (cols + ct - 1) / ct;
     const int64_t n_segs = bands * rows;
     hipLaunchKernelGGL(compact_rows_kernel<INT>, dim3((unsigned)((n_segs + 3) / 4)), dim3(256), 0,
-                       s, static_cast<const uint32_t*>(M), ld, rows, cols, ct, n_segs, ent, lens);
+                       s, static_cast<const uint32_t*>(M), ld, rows, cols, ct, n_segs, ent, lens,
+                       gate);
     return hipGetLastError();
 }
 
 hipError_t launch_compact_rows(int case_id, const void* X, int64_t ldx, const void* Y,
                                int64_t ldy, int m, int kd, int n, int C, const RowsLists& L,
-                               hipStream_t s) {
+                               hipStream_t s, const uint32_t* gate) {
     const bool x_int = case_id == 1;  // case B: X holds the counts
     // X: one band as wide as its row (capacity xcap)
-    hipError_t e = x_int ? launch_compact<true>(X, ldx, m, kd, (int)L.xcap, L.xent, L.xlen, s)
-                         : launch_compact<false>(X, ldx, m, kd, (int)L.xcap, L.xent, L.xlen, s);
+    hipError_t e = x_int ? launch_compact<true>(X, ldx, m, kd, (int)L.xcap, L.xent, L.xlen, s, gate)
+                         : launch_compact<false>(X, ldx, m, kd, (int)L.xcap, L.xent, L.xlen, s, gate);
     if (e != hipSuccess) return e;
-    return x_int ? launch_compact<false>(Y, ldy, kd, n, kWave * C, L.yent, L.ylen, s)
-                 : launch_compact<true>(Y, ldy, kd, n, kWave * C, L.yent, L.ylen, s);
+    return x_int ? launch_compact<false>(Y, ldy, kd, n, kWave * C, L.yent, L.ylen, s, gate)
+                 : launch_compact<true>(Y, ldy, kd, n, kWave * C, L.yent, L.ylen, s, gate);
 }
 
 template <int C, int W>
@@ -118,9 +121,11 @@ template <int C, int W, bool CASE_A>
 __global__ __launch_bounds__(W * kWave) void rep_rows_kernel(
     int m, int kd, int n, const uint2* __restrict__ xent, const int32_t* __restrict__ xlen,
     int64_t xcap, const uint2* __restrict__ yent, const int32_t* __restrict__ ylen,
-    float* __restrict__ Z, int64_t ldz, int n_row_blocks, int n_tiles) {
+    float* __restrict__ Z, int64_t ldz, int n_row_blocks, int n_tiles,
+    const uint32_t* __restrict__ gate) {
     using T = RowsTile<C, W>;
     __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    AFMM_GATE(gate);
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     const int lane = threadIdx.x & (kWave - 1);
@@ -207,17 +212,17 @@ __global__ __launch_bounds__(W * kWave) void rep_rows_kernel(
 
 template <int C, int W>
 hipError_t launch_rows(int case_id, int m, int kd, int n, const RowsLists& L, float* Z,
-                       int64_t ldz, hipStream_t s) {
+                       int64_t ldz, hipStream_t s, const uint32_t* gate) {
     using T = RowsTile<C, W>;
     const int n_row_blocks = (m + W - 1) / W;
     const int n_tiles = n_row_blocks * ((n + T::CT - 1) / T::CT);
     dim3 grid(n_tiles), block(W * kWave);
     if (case_id == 0)
         hipLaunchKernelGGL((rep_rows_kernel<C, W, true>), grid, block, 0, s, m, kd, n, L.xent,
-                           L.xlen, L.xcap, L.yent, L.ylen, Z, ldz, n_row_blocks, n_tiles);
+                           L.xlen, L.xcap, L.yent, L.ylen, Z, ldz, n_row_blocks, n_tiles, gate);
     else
         hipLaunchKernelGGL((rep_rows_kernel<C, W, false>), grid, block, 0, s, m, kd, n, L.xent,
-                           L.xlen, L.xcap, L.yent, L.ylen, Z, ldz, n_row_blocks, n_tiles);
+                           L.xlen, L.xcap, L.yent, L.ylen, Z, ldz, n_row_blocks, n_tiles, gate);
     return hipGetLastError();
 }
 
@@ -238,9 +243,9 @@ bool rep_rows_supported(int R, int C, int W, int U, int KP) {
 }
 
 hipError_t launch_rep_rows(int case_id, int m, int kd, int n, const RowsLists& L, float* Z,
-                           int64_t ldz, int C, int W, hipStream_t s) {
+                           int64_t ldz, int C, int W, hipStream_t s, const uint32_t* gate) {
 #define AFMM_CASE(c, w) \
-    if (C == c && W == w) return launch_rows<c, w>(case_id, m, kd, n, L, Z, ldz, s);
+    if (C == c && W == w) return launch_rows<c, w>(case_id, m, kd, n, L, Z, ldz, s, gate);
     AFMM_ROWS_CONFIGS(AFMM_CASE)
 #undef AFMM_CASE
     return hipErrorInvalidValue;
@@ -280,6 +285,69 @@ hipError_t launch_count_nonzero(bool is_int, const void* M, int64_t ld, int rows
     else
         hipLaunchKernelGGL(count_nonzero_kernel<false>, dim3(blocks), dim3(256), 0, s,
                            static_cast<const uint32_t*>(M), ld, rows, cols, o);
+    return hipGetLastError();
+}
+
+// Block b < kChooseRows counts row b of the real factor's sample, the next
+// kChooseRows blocks the integer factor's; a sample row is the middle of its
+// stratum of rows / s_eff rows.
+__global__ __launch_bounds__(256) void choose_count_kernel(ChooseArgs a,
+                                                           unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long wsum[4];
+    const bool is_int = blockIdx.x >= (unsigned)kChooseRows;
+    const int t = (int)blockIdx.x - (is_int ? kChooseRows : 0);
+    const int rows = is_int ? a.i_rows : a.r_rows, cols = is_int ? a.i_cols : a.r_cols;
+    const int s_eff = rows < kChooseRows ? rows : kChooseRows;
+    unsigned long long c = 0;
+    if (t < s_eff) {
+        const int64_t r = ((int64_t)(2 * t + 1) * rows) / (2 * s_eff);
+        const uint32_t* row = static_cast<const uint32_t*>(is_int ? a.I : a.R) +
+                              r * (is_int ? a.ldi : a.ldr);
+        for (int col = threadIdx.x; col < cols; col += 256) {
+            const uint32_t v = row[col];
+            c += (is_int ? (int32_t)v > 0 : __uint_as_float(v) != 0.0f) ? 1u : 0u;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__global__ __launch_bounds__(64) void choose_decide_kernel(ChooseArgs a,
+                                                           const unsigned long long* __restrict__ part,
+                                                           uint32_t* __restrict__ gates) {
+    const int lane = threadIdx.x;
+    unsigned long long cr = part[lane] + part[lane + 64];
+    unsigned long long ci = part[kChooseRows + lane] + part[kChooseRows + lane + 64];
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        cr += __shfl_down(cr, off);
+        ci += __shfl_down(ci, off);
+    }
+    if (lane != 0) return;
+    const int sr = a.r_rows < kChooseRows ? a.r_rows : kChooseRows;
+    const int si = a.i_rows < kChooseRows ? a.i_rows : kChooseRows;
+    const double d_real = (double)cr / ((double)sr * (double)a.r_cols);
+    const double d_int = (double)ci / ((double)si * (double)a.i_cols);
+    int sel = 0;
+    if (d_real * d_int * a.size <= a.row_list_max)
+        sel = 7;
+    else if (a.allow_sparse_real && d_real <= a.sparse_real_max)
+        sel = 4;
+    gates[0] = sel == 0;
+    gates[1] = sel != 7;
+    gates[2] = sel == 4;
+    gates[3] = sel == 7;
+    if (a.chosen) *a.chosen = sel == 0 ? a.default_mapping : sel;
+}
+
+hipError_t launch_choose_form(const ChooseArgs& a, uint8_t* ctl, hipStream_t s) {
+    static_assert(kChooseRows == 128, "the decision sums two sample rows per lane");
+    auto* part = reinterpret_cast<unsigned long long*>(ctl);
+    hipLaunchKernelGGL(choose_count_kernel, dim3(2 * kChooseRows), dim3(256), 0, s, a, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(choose_decide_kernel, dim3(1), dim3(64), 0, s, a, part, choose_gates(ctl));
     return hipGetLastError();
 }
 

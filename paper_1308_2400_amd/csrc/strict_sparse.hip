@@ -11,9 +11,10 @@ rep_sparse_kernel(int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int
                   const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk,
                   const float* __restrict__ Q, int64_t ldq, float* __restrict__ Z, int64_t z_sr,
                   int64_t z_sc, const uint32_t* __restrict__ esc, int n_row_blocks,
-                  int n_tiles) {
+                  int n_tiles, const uint32_t* __restrict__ gate) {
     using T = SparseTile<R, C, W, KP>;
     __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    AFMM_GATE(gate);
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     if (*esc)
@@ -36,11 +37,11 @@ hipError_t launch_sparse(const StrictArgs& a, hipStream_t s) {
     if (a.trans_out)
         hipLaunchKernelGGL((rep_sparse_kernel<R, C, W, U, KP, true>), grid, block, 0, s, a.n_r,
                            a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z,
-                           a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles);
+                           a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     else
         hipLaunchKernelGGL((rep_sparse_kernel<R, C, W, U, KP, false>), grid, block, 0, s, a.n_r,
                            a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, a.Q, a.ldq, a.Z,
-                           a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles);
+                           a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     return hipGetLastError();
 }
 

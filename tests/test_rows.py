@@ -128,3 +128,67 @@ def test_suggested_configuration(dev, case):
         assert np.array_equal(_bits(Z.cpu().numpy()), _bits(Zd.cpu().numpy()))
     X, Y = _inputs(case, 512, 5, 0.05, 0.05)
     assert afmm.suggest_config(case, _to(dev, X), _to(dev, Y)) == afmm.default_config(case, 512)
+
+
+# Plain calls choose their form on the device: (d_real, d_int) and the mapping
+# the choice must land on ("dense": the size-keyed one).  Positive counts are
+# 6/7 of the integer mask with int_lo = 0.
+PLAIN_REGIMES = [(0.6, 0.7, "dense"), (0.05, 0.95, 4), (0.03, 0.05, 7)]
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("n", [1031, 2085])
+@pytest.mark.parametrize("regime", PLAIN_REGIMES, ids=lambda r: str(r[2]))
+def test_plain_call_chooses_form_bitexact(dev, case, n, regime):
+    """afmm_multiply_caseA / caseB without a configuration, on ragged sizes in
+    the three density regimes: the form the device picks (read back through
+    afmm_plain_form) is the one the full-density rule names, and the result is
+    bit-exact on sampled rows and identical in full to that form run
+    explicitly, with a caller workspace of exactly afmm_workspace_size bytes."""
+    import torch
+    afmm = _afmm()
+    d_real, d_int, want = regime
+    X, Y = _inputs(case, n, 910 + n + int(100 * d_real), d_real, d_int, int_hi=300)
+    Xd, Yd = _to(dev, X), _to(dev, Y)
+    form = afmm.plain_form(case, Xd, Yd)
+    if want == "dense":
+        assert form == afmm.default_config(case, n)[0]
+    else:
+        assert form == want
+    assert afmm.suggest_config(case, Xd, Yd)[0] == form
+    ws = torch.empty(afmm.workspace_size(case, n), dtype=torch.uint8, device=dev)
+    Z = afmm.multiply(case, Xd, Yd, workspace=ws).cpu().numpy()
+    rows = [0, 1, n // 2, n - 1]
+    Zr, _ = oracle.strict_f32(case, X[rows], Y, rows=rows, x_rows_only=True)
+    assert np.array_equal(_bits(Z[rows]), _bits(Zr))
+    Ze = afmm.multiply(case, Xd, Yd, config=afmm.suggest_config(case, Xd, Yd)).cpu().numpy()
+    assert np.array_equal(_bits(Z), _bits(Ze))
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+def test_plain_call_quadratic_regime(dev, case):
+    """n = 4096, d1 * d2 = 1/n: the plain call takes the row-list form and its
+    sampled rows are bit-exact; a workspace one byte short is refused."""
+    import torch
+    afmm = _afmm()
+    n, d = 4096, 1.0 / 64
+    w = gen.Workload(f"quad_{case}", case, n, gen.RealSpec(gen.UNIFORMPM1, d),
+                     gen.IntSpec(gen.INT_UNIFORM, d, 1, 7), 9100 + (case == "B"))
+    X, Y = w.X(), w.Y()
+    Xd, Yd = _to(dev, X), _to(dev, Y)
+    assert afmm.plain_form(case, Xd, Yd) == 7
+    Z = afmm.multiply(case, Xd, Yd).cpu().numpy()
+    rows = [0, 17, 2048, 4095]
+    Zr, _ = oracle.strict_f32(case, X[rows], Y, rows=rows, x_rows_only=True)
+    assert np.array_equal(_bits(Z[rows]), _bits(Zr))
+    short = torch.empty(afmm.workspace_size(case, n) - 1, dtype=torch.uint8, device=dev)
+    with pytest.raises(afmm.AfmmError):
+        afmm.multiply(case, Xd, Yd, workspace=short)
+
+
+def test_plain_call_small_keeps_size_keyed_form(dev):
+    """Below n = 1024 the plain call keeps the size-keyed form whatever the density."""
+    afmm = _afmm()
+    for case in "AB":
+        X, Y = _inputs(case, 700, 4, 0.02, 0.02)
+        assert afmm.plain_form(case, _to(dev, X), _to(dev, Y)) == afmm.default_config(case, 700)[0]
