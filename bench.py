@@ -341,7 +341,7 @@ def empirical_fit(rows):
 
 # compacted-base configuration for a real factor with few non-zeros (autotuner's
 # pick on the n=16384 case-A distribution at n = 2048..8192)
-SPARSE_REAL_CONFIG = (4, 2, 32, 8, 2, 8)
+SPARSE_REAL_CONFIG = (4, 2, 16, 8, 1, 16)
 
 
 def c5(args):

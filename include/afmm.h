@@ -258,7 +258,7 @@ size_t afmm_workspace_size_config(afmm_case c, int64_t n, const afmm_config *cfg
  * the densities of the two factors, counted on the device (the call waits for
  * `stream`): with d_real the fraction of non-zero real entries and d_int that
  * of positive counts, the form over the non-zeros of both factors (mapping 7)
- * when d_real * d_int * n <= 32 (case A) or 42 (case B), else the
+ * when d_real * d_int * n <= 32 (case A) or 64 (case B), else the
  * compacted-base form (mapping 4) when
  * d_real <= 0.06, otherwise afmm_default_config (also for n < 1024).  The
  * thresholds come from measurements on MI355X; every configuration gives the

@@ -330,13 +330,14 @@ constexpr int64_t kAdaptMin = 1024;
 // The two forms for sparse factors the plain call may choose instead of the
 // size-keyed one (what afmm_suggest_config returns).
 afmm_config sparse_real_config(int64_t size) {
-    return size <= 2896 ? afmm_config{4, 1, 64, 8, 2, 8} : afmm_config{4, 2, 32, 8, 2, 8};
+    (void)size;  // the best compacted-base shape at n = 2048 .. 16384
+    return afmm_config{4, 2, 16, 8, 1, 16};
 }
 afmm_config row_list_config(int64_t size) {
     return afmm_config{7, 1, size <= 2896 ? 16 : 32, 16, 1, 16};
 }
 // d_real * d_int * size at or below which the row-list form wins
-double row_list_threshold(afmm_case c) { return c == AFMM_CASE_A ? 32.0 : 42.0; }
+double row_list_threshold(afmm_case c) { return c == AFMM_CASE_A ? 32.0 : 64.0; }
 constexpr double kSparseRealMax = 0.06;  // d_real at or below which the compacted base wins
 
 // Above this size the lists of the two sparse forms (up to 24 bytes per entry
@@ -656,7 +657,7 @@ afmm_status afmm_suggest_config(afmm_case c, int64_t n, const void* X, const voi
     // thresholds from measurements on MI355X (n = 2048..16384): the row-list form
     // while a row meets few non-zero pairs per k (d_real * d_int * n, its work per
     // k of a row, is at most 32 in case A, where a lane loops its own count, and
-    // 42 in case B), the compacted-base form when the real factor alone is very
+    // 64 in case B), the compacted-base form when the real factor alone is very
     // sparse, the size-keyed choice otherwise
     if (d_real * d_int * (double)n <= row_list_threshold(c))
         *out = row_list_config(n);

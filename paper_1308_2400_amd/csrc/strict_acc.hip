@@ -10,6 +10,8 @@
 // additions in ascending k, a k's repetitions consecutively, so the result is
 // bit-identical to the other forms.  A wave owns its rows, so no two waves
 // touch one element and the k loop has no barrier.
+#include <utility>
+
 #include "sparse_body.hpp"
 #include "strict_acc.hpp"
 
@@ -34,49 +36,112 @@ AccLists acc_lists_at(uint8_t* p, int n_c, int n_k, int C) {
     return L;
 }
 
-// One wave per segment (band, k): ballot the non-zero bases of 64 columns at
-// a time and write them at their rank.  Segments with k >= n_k get length 0.
+// One wave per segment (band, k).  Lane l owns the band's columns l + 64 m
+// (m < C), all of one residue modulo 64; an element (row, column) of the Z
+// tile sits in LDS bank (row offset + column) mod 64 (and mod 32), so lanes
+// that take columns of distinct residues read and write a row without bank
+// conflicts.  With total non-zero bases in the band, the segment gets
+// nch = ceil(total / 64) chunks of 64 slots: slot (q, l) holds lane l's q-th
+// non-zero column when it has one (its own residue), lanes with more than nch
+// non-zero columns hand the rest to the free slots of other lanes (these share
+// a bank with their owner), and slots left over get the lane's sink column
+// CT + l with a +0.0 base.  The chunks are padded to a multiple of E (the
+// entries a lane takes per k).  An entry is {bits of the base, byte offset of
+// its column in an LDS row}; the segment's length is the padded slot count, 0
+// when the band has no non-zero base at this k.  Which slot adds a base
+// changes nothing in the sums: each column appears once per k.
 __global__ __launch_bounds__(256) void compact_base_kernel(const float* __restrict__ Q,
-                                                           int64_t ldq, int n_k, int n_c, int ct,
-                                                           int64_t n_k_pad, int64_t n_segs,
+                                                           int64_t ldq, int n_k, int n_c, int C,
+                                                           int E, int64_t n_k_pad, int64_t n_segs,
                                                            uint2* __restrict__ ent,
                                                            int32_t* __restrict__ lens,
                                                            const uint32_t* __restrict__ gate) {
+    // per wave: the columns handed on, in hand-over order (CT <= 4096 of them)
+    __shared__ uint16_t handed[4][kWave * 64];
     AFMM_GATE(gate);
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
     if (seg >= n_segs) return;  // whole waves
+    const int ct = kWave * C;
     const int band = (int)(seg / n_k_pad);
     const int k = (int)(seg - (int64_t)band * n_k_pad);
-    int count = 0;
+    const int c0 = band * ct;
+    uint64_t mine = 0;  // bit m: column lane + 64 m is non-zero
+    const float* __restrict__ q = Q + (int64_t)k * ldq + c0;
     if (k < n_k) {
-        const float* __restrict__ q = Q + (int64_t)k * ldq + (int64_t)band * ct;
-        const int cols = min(ct, n_c - band * ct);
-        uint2* __restrict__ out = ent + seg * ct;
-        for (int ch = 0; ch < cols; ch += kWave) {
-            const int c = ch + lane;
-            const float v = c < cols ? q[c] : 0.0f;
-            const bool nz = v != 0.0f;  // IEEE: -0 is zero, NaN is not
-            const uint64_t m = __ballot(nz);
-            if (nz) {
-                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                out[count + (int)below] = make_uint2(__float_as_uint(v), (uint32_t)c);
-            }
-            count += __popcll(m);
+        for (int m = 0; m < C; ++m) {
+            const int c = lane + kWave * m;
+            const float v = c0 + c < n_c ? q[c] : 0.0f;
+            if (v != 0.0f) mine |= (uint64_t)1 << m;  // IEEE: -0 is zero, NaN is not
         }
     }
-    if (lane == 0) lens[seg] = count;
+    const int a = __popcll(mine);
+    int total = a;
+    for (int off = kWave / 2; off > 0; off >>= 1) total += __shfl_xor(total, off);
+    if (total == 0) {
+        if (lane == 0) lens[seg] = 0;
+        return;
+    }
+    const int nch = (total + kWave - 1) / kWave;
+    const int npad = (nch + E - 1) / E * E;
+    uint2* __restrict__ out = ent + seg * ct;
+    const uint2 sink = make_uint2(0u, (uint32_t)(ct + lane) * 4u);
+    // the lane's own columns into its first min(a, nch) slots
+    uint64_t rest = mine;
+    const int own = a < nch ? a : nch;
+    for (int s = 0; s < own; ++s) {
+        const int m = __ffsll((unsigned long long)rest) - 1;
+        rest &= rest - 1;
+        const int c = lane + kWave * m;
+        out[s * kWave + lane] = make_uint2(__float_as_uint(q[c]), (uint32_t)c * 4u);
+    }
+    // columns beyond nch go to the free slots of lanes with fewer than nch
+    const int ov = a - own, holes = nch - own;
+    int ov_x = ov, h_x = holes;  // inclusive scans over the lanes
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t1 = __shfl_up(ov_x, off), t2 = __shfl_up(h_x, off);
+        if (lane >= off) {
+            ov_x += t1;
+            h_x += t2;
+        }
+    }
+    const int ov_total = __shfl(ov_x, kWave - 1);
+    ov_x -= ov;
+    h_x -= holes;
+    if (ov_total > 0) {
+        for (int u = 0; u < ov; ++u) {
+            const int m = __ffsll((unsigned long long)rest) - 1;
+            rest &= rest - 1;
+            handed[wv][ov_x + u] = (uint16_t)(lane + kWave * m);
+        }
+        // the wave's own LDS writes, read back by other lanes of the wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int s = own; s < nch; ++s) {
+        const int t = h_x + (s - own);
+        uint2 e = sink;
+        if (t < ov_total) {
+            const int c = handed[wv][t];
+            e = make_uint2(__float_as_uint(q[c]), (uint32_t)c * 4u);
+        }
+        out[s * kWave + lane] = e;
+    }
+    for (int s = nch; s < npad; ++s) out[s * kWave + lane] = sink;
+    if (lane == 0) lens[seg] = npad * kWave;
 }
 
 hipError_t launch_compact_base(const float* Q, int64_t ldq, int n_k, int n_c, int C,
                                const AccLists& L, hipStream_t s, const uint32_t* gate) {
     const int ct = kWave * C;
+    if (C < 1 || C > 64) return hipErrorInvalidValue;
+    const int E = C >= 16 ? C / 16 : 1;  // entries a lane takes per k (AccTile::E)
     const int64_t bands = (n_c + ct - 1) / ct;
     const int64_t n_segs = bands * L.n_k_pad;
     const int64_t blocks = (n_segs + 3) / 4;
     hipLaunchKernelGGL(compact_base_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Q, ldq, n_k,
-                       n_c, ct, L.n_k_pad, n_segs, L.ent, L.lens, gate);
+                       n_c, C, E, L.n_k_pad, n_segs, L.ent, L.lens, gate);
     return hipGetLastError();
 }
 
@@ -97,64 +162,466 @@ struct AccTile {
     static_assert(kKPad % KP == 0, "KP must divide the k padding");
 };
 
-// One chunk of up to 64*E entries of the segment of k0 + kk, slot q of lane l
-// holding entry ch_ + 64 q + l: a slot past the segment's end turns into a +0.0
-// base on the lane's sink column, so every lane runs every slot.  Each of the
-// wave's rows with a non-zero count reads its E Z elements from LDS, adds each
-// slot's base `rep` times (the E chains side by side) and writes them back; the
-// reads of all rows go out before the first addition.
-#define AFMM_ACC_CHUNK(ev_, ch_)                                                               \
+// 32-bit LDS addresses: of a pointer into a __shared__ array, and back.
+typedef __attribute__((address_space(3))) float lds_float;
+__device__ __forceinline__ uint32_t lds_address(float* p) {
+    return (uint32_t)(uintptr_t)(lds_float*)p;
+}
+__device__ __forceinline__ lds_float* lds_at(uint32_t a) { return (lds_float*)(uintptr_t)a; }
+
+// The per-row work of one chunk, for waves of one or two rows, as assembly:
+// the compiler turns the skip of a row with a zero count into mask juggling on
+// the vector unit, and its repetition loops into three scalar instructions a
+// round.  acc_read issues the E reads of every row with a non-zero count and
+// waits for them in the same block (no load is left in flight when it ends);
+// acc_row adds each slot's base n times and writes the E elements back.  OFF
+// is the row's byte offset in LDS.
+#define AFMM_RD(z_, a_, o_) "ds_read_b32 %[" z_ "], %[" a_ "] offset:%[" o_ "]\n\t"
+#define AFMM_WR(z_, a_) "ds_write_b32 %[" a_ "], %[" z_ "] offset:%[o]\n\t"
+#define AFMM_ADD(z_, b_) "v_add_f32 %[" z_ "], %[" b_ "], %[" z_ "]\n\t"
+
+template <int E, int R>
+struct AccAsm;
+
+template <>
+struct AccAsm<1, 1> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[2][1], const uint32_t (&n)[1],
+                                                const uint32_t (&a)[1]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z0", "a0", "o0")
+                     "1:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z0] "=&v"(z[0][0])
+                     : [n0] "s"(n[0]), [a0] "v"(a[0]), [o0] "i"(0)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccAsm<1, 2> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[2][1], const uint32_t (&n)[2],
+                                                const uint32_t (&a)[1]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z0", "a0", "o0")
+                     "1:\n\ts_cmp_eq_u32 %[n1], 0\n\ts_cbranch_scc1 2f\n\t"
+                     AFMM_RD("z1", "a0", "o1") "2:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z0] "=&v"(z[0][0]), [z1] "=&v"(z[1][0])
+                     : [n0] "s"(n[0]), [n1] "s"(n[1]), [a0] "v"(a[0]), [o0] "i"(0), [o1] "i"(O)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccAsm<2, 1> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[2][2], const uint32_t (&n)[1],
+                                                const uint32_t (&a)[2]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z00", "a0", "o0")
+                     AFMM_RD("z01", "a1", "o0") "1:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z00] "=&v"(z[0][0]), [z01] "=&v"(z[0][1])
+                     : [n0] "s"(n[0]), [a0] "v"(a[0]), [a1] "v"(a[1]), [o0] "i"(0)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccAsm<2, 2> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[2][2], const uint32_t (&n)[2],
+                                                const uint32_t (&a)[2]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z00", "a0", "o0")
+                     AFMM_RD("z01", "a1", "o0") "1:\n\ts_cmp_eq_u32 %[n1], 0\n\t"
+                     "s_cbranch_scc1 2f\n\t" AFMM_RD("z10", "a0", "o1") AFMM_RD("z11", "a1", "o1")
+                     "2:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z00] "=&v"(z[0][0]), [z01] "=&v"(z[0][1]), [z10] "=&v"(z[1][0]),
+                       [z11] "=&v"(z[1][1])
+                     : [n0] "s"(n[0]), [n1] "s"(n[1]), [a0] "v"(a[0]), [a1] "v"(a[1]),
+                       [o0] "i"(0), [o1] "i"(O)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccAsm<4, 1> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[2][4], const uint32_t (&n)[1],
+                                                const uint32_t (&a)[4]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z00", "a0", "o0")
+                     AFMM_RD("z01", "a1", "o0") AFMM_RD("z02", "a2", "o0")
+                     AFMM_RD("z03", "a3", "o0") "1:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z00] "=&v"(z[0][0]), [z01] "=&v"(z[0][1]), [z02] "=&v"(z[0][2]),
+                       [z03] "=&v"(z[0][3])
+                     : [n0] "s"(n[0]), [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]),
+                       [a3] "v"(a[3]), [o0] "i"(0)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccAsm<4, 2> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[2][4], const uint32_t (&n)[2],
+                                                const uint32_t (&a)[4]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z00", "a0", "o0")
+                     AFMM_RD("z01", "a1", "o0") AFMM_RD("z02", "a2", "o0")
+                     AFMM_RD("z03", "a3", "o0") "1:\n\ts_cmp_eq_u32 %[n1], 0\n\t"
+                     "s_cbranch_scc1 2f\n\t" AFMM_RD("z10", "a0", "o1") AFMM_RD("z11", "a1", "o1")
+                     AFMM_RD("z12", "a2", "o1") AFMM_RD("z13", "a3", "o1")
+                     "2:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z00] "=&v"(z[0][0]), [z01] "=&v"(z[0][1]), [z02] "=&v"(z[0][2]),
+                       [z03] "=&v"(z[0][3]), [z10] "=&v"(z[1][0]), [z11] "=&v"(z[1][1]),
+                       [z12] "=&v"(z[1][2]), [z13] "=&v"(z[1][3])
+                     : [n0] "s"(n[0]), [n1] "s"(n[1]), [a0] "v"(a[0]), [a1] "v"(a[1]),
+                       [a2] "v"(a[2]), [a3] "v"(a[3]), [o0] "i"(0), [o1] "i"(O)
+                     : "scc", "memory");
+    }
+};
+
+// acc_row: n = 0 skips the row (no write); otherwise a scalar down-counter
+// whose borrow ends the loop (two scalar instructions a round).  A binary
+// decomposition (1, 2, 4 additions under forward skips, then rounds of 8)
+// measured 3 % slower on the n=16384 case-A workload.
+template <>
+struct AccAsm<1, 4> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[4][1], const uint32_t (&n)[4],
+                                                const uint32_t (&a)[1]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z0", "a0", "o0")
+                     "1:\n\ts_cmp_eq_u32 %[n1], 0\n\ts_cbranch_scc1 2f\n\t" AFMM_RD("z1", "a0", "o1")
+                     "2:\n\ts_cmp_eq_u32 %[n2], 0\n\ts_cbranch_scc1 3f\n\t" AFMM_RD("z2", "a0", "o2")
+                     "3:\n\ts_cmp_eq_u32 %[n3], 0\n\ts_cbranch_scc1 4f\n\t" AFMM_RD("z3", "a0", "o3")
+                     "4:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z0] "=&v"(z[0][0]), [z1] "=&v"(z[1][0]), [z2] "=&v"(z[2][0]),
+                       [z3] "=&v"(z[3][0])
+                     : [n0] "s"(n[0]), [n1] "s"(n[1]), [n2] "s"(n[2]), [n3] "s"(n[3]),
+                       [a0] "v"(a[0]), [o0] "i"(0), [o1] "i"(O), [o2] "i"(2 * O), [o3] "i"(3 * O)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccAsm<2, 4> {
+    template <int O>
+    __device__ __forceinline__ static void read(float (&z)[4][2], const uint32_t (&n)[4],
+                                                const uint32_t (&a)[2]) {
+        asm volatile("s_cmp_eq_u32 %[n0], 0\n\ts_cbranch_scc1 1f\n\t" AFMM_RD("z00", "a0", "o0")
+                     AFMM_RD("z01", "a1", "o0")
+                     "1:\n\ts_cmp_eq_u32 %[n1], 0\n\ts_cbranch_scc1 2f\n\t" AFMM_RD("z10", "a0", "o1")
+                     AFMM_RD("z11", "a1", "o1")
+                     "2:\n\ts_cmp_eq_u32 %[n2], 0\n\ts_cbranch_scc1 3f\n\t" AFMM_RD("z20", "a0", "o2")
+                     AFMM_RD("z21", "a1", "o2")
+                     "3:\n\ts_cmp_eq_u32 %[n3], 0\n\ts_cbranch_scc1 4f\n\t" AFMM_RD("z30", "a0", "o3")
+                     AFMM_RD("z31", "a1", "o3") "4:\n\ts_waitcnt lgkmcnt(0)"
+                     : [z00] "=&v"(z[0][0]), [z01] "=&v"(z[0][1]), [z10] "=&v"(z[1][0]),
+                       [z11] "=&v"(z[1][1]), [z20] "=&v"(z[2][0]), [z21] "=&v"(z[2][1]),
+                       [z30] "=&v"(z[3][0]), [z31] "=&v"(z[3][1])
+                     : [n0] "s"(n[0]), [n1] "s"(n[1]), [n2] "s"(n[2]), [n3] "s"(n[3]),
+                       [a0] "v"(a[0]), [a1] "v"(a[1]), [o0] "i"(0), [o1] "i"(O),
+                       [o2] "i"(2 * O), [o3] "i"(3 * O)
+                     : "scc", "memory");
+    }
+};
+
+template <int E>
+struct AccRow;
+template <>
+struct AccRow<1> {
+    template <int O>
+    __device__ __forceinline__ static void run(float (&z)[1], const float (&b)[1], uint32_t n,
+                                               const uint32_t (&a)[1]) {
+        uint32_t t;
+        asm volatile("s_sub_u32 %[t], %[n], 1\n\ts_cbranch_scc1 2f\n"
+                     "1:\n\t" AFMM_ADD("z0", "b0")
+                     "s_sub_u32 %[t], %[t], 1\n\ts_cbranch_scc0 1b\n\t" AFMM_WR("z0", "a0") "2:"
+                     : [z0] "+v"(z[0]), [t] "=&s"(t)
+                     : [n] "s"(n), [b0] "v"(b[0]), [a0] "v"(a[0]), [o] "i"(O)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccRow<2> {
+    template <int O>
+    __device__ __forceinline__ static void run(float (&z)[2], const float (&b)[2], uint32_t n,
+                                               const uint32_t (&a)[2]) {
+        uint32_t t;
+        asm volatile("s_sub_u32 %[t], %[n], 1\n\ts_cbranch_scc1 2f\n"
+                     "1:\n\t" AFMM_ADD("z0", "b0") AFMM_ADD("z1", "b1")
+                     "s_sub_u32 %[t], %[t], 1\n\ts_cbranch_scc0 1b\n\t" AFMM_WR("z0", "a0")
+                     AFMM_WR("z1", "a1") "2:"
+                     : [z0] "+v"(z[0]), [z1] "+v"(z[1]), [t] "=&s"(t)
+                     : [n] "s"(n), [b0] "v"(b[0]), [b1] "v"(b[1]), [a0] "v"(a[0]),
+                       [a1] "v"(a[1]), [o] "i"(O)
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccRow<4> {
+    template <int O>
+    __device__ __forceinline__ static void run(float (&z)[4], const float (&b)[4], uint32_t n,
+                                               const uint32_t (&a)[4]) {
+        uint32_t t;
+        asm volatile("s_sub_u32 %[t], %[n], 1\n\ts_cbranch_scc1 2f\n"
+                     "1:\n\t" AFMM_ADD("z0", "b0") AFMM_ADD("z1", "b1") AFMM_ADD("z2", "b2")
+                     AFMM_ADD("z3", "b3") "s_sub_u32 %[t], %[t], 1\n\ts_cbranch_scc0 1b\n\t"
+                     AFMM_WR("z0", "a0") AFMM_WR("z1", "a1") AFMM_WR("z2", "a2")
+                     AFMM_WR("z3", "a3") "2:"
+                     : [z0] "+v"(z[0]), [z1] "+v"(z[1]), [z2] "+v"(z[2]), [z3] "+v"(z[3]),
+                       [t] "=&s"(t)
+                     : [n] "s"(n), [b0] "v"(b[0]), [b1] "v"(b[1]), [b2] "v"(b[2]),
+                       [b3] "v"(b[3]), [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]),
+                       [a3] "v"(a[3]), [o] "i"(O)
+                     : "scc", "memory");
+    }
+};
+#undef AFMM_RD
+#undef AFMM_WR
+#undef AFMM_ADD
+
+// z[q] += b[q], n times over (n >= 1), for waves of more than two rows
+// (compiled loop).
+template <int E>
+__device__ __forceinline__ void add_times(float (&z)[E], const float (&b)[E], uint32_t n) {
+    do {
+#pragma unroll
+        for (int q = 0; q < E; ++q) z[q] = z[q] + b[q];
+    } while (--n != 0);
+}
+
+// The common k in one block of assembly, for waves of one or two rows and a
+// segment of exactly one group of 64*E slots (no escaped counts): each row's
+// count is cut from its count word with s_bfe, whose SCC (count != 0) drives
+// the branch, so a row costs two scalar instructions before its loads; with
+// two rows, four paths (both rows, either, none) avoid testing a count twice,
+// and row 1's reads are in flight while row 0 adds.  No load is left in flight
+// when the block ends (its writes may be).
+template <int R, int E>
+struct AccK;
+
+#define AFMM_LOOP(L_, N_, ADD_, WR_)                                                           \
+    "s_sub_u32 %[t], %[" N_ "], 1\n" L_ ":\n\t" ADD_                                          \
+    "s_sub_u32 %[t], %[t], 1\n\ts_cbranch_scc0 " L_ "b\n\t" WR_
+#define AFMM_ONE_ROW(RD0, AD0, WR0)                                                            \
+    "s_bfe_u32 %[n0], %[w0], %[i0]\n\ts_cbranch_scc0 90f\n\t" RD0                              \
+    "s_waitcnt lgkmcnt(0)\n\t" AFMM_LOOP("11", "n0", AD0, WR0) "90:"
+#define AFMM_TWO_ROWS(EL, RD0, RD1, AD0, AD1, WR0, WR1)                                        \
+    "s_bfe_u32 %[n0], %[w0], %[i0]\n\ts_cbranch_scc0 50f\n\t"                                  \
+    "s_bfe_u32 %[n1], %[w1], %[i1]\n\ts_cbranch_scc0 30f\n\t" RD0 RD1                          \
+    "s_waitcnt lgkmcnt(" EL ")\n\t" AFMM_LOOP("11", "n0", AD0, WR0)                            \
+    "s_waitcnt lgkmcnt(" EL ")\n\t" AFMM_LOOP("12", "n1", AD1, WR1) "s_branch 90f\n"           \
+    "30:\n\t" RD0 "s_waitcnt lgkmcnt(0)\n\t" AFMM_LOOP("13", "n0", AD0, WR0) "s_branch 90f\n"  \
+    "50:\n\ts_bfe_u32 %[n1], %[w1], %[i1]\n\ts_cbranch_scc0 90f\n\t" RD1                       \
+    "s_waitcnt lgkmcnt(0)\n\t" AFMM_LOOP("14", "n1", AD1, WR1) "90:"
+
+#define AFMM_RD0(q) "ds_read_b32 %[z0" #q "], %[a" #q "]\n\t"
+#define AFMM_RD1(q) "ds_read_b32 %[z1" #q "], %[a" #q "] offset:%[o1]\n\t"
+#define AFMM_AD0(q) "v_add_f32 %[z0" #q "], %[b" #q "], %[z0" #q "]\n\t"
+#define AFMM_AD1(q) "v_add_f32 %[z1" #q "], %[b" #q "], %[z1" #q "]\n\t"
+#define AFMM_WR0(q) "ds_write_b32 %[a" #q "], %[z0" #q "]\n\t"
+#define AFMM_WR1(q) "ds_write_b32 %[a" #q "], %[z1" #q "] offset:%[o1]\n\t"
+#define AFMM_X1(M) M(0)
+#define AFMM_X2(M) M(0) M(1)
+#define AFMM_X4(M) M(0) M(1) M(2) M(3)
+
+template <>
+struct AccK<1, 1> {
+    template <int I0, int O1>
+    __device__ __forceinline__ static void run(const uint32_t (&w)[1], const uint32_t (&a)[1],
+                                               const float (&b)[1]) {
+        float z00;
+        uint32_t n0, t;
+        asm volatile(AFMM_ONE_ROW(AFMM_X1(AFMM_RD0), AFMM_X1(AFMM_AD0), AFMM_X1(AFMM_WR0))
+                     : [z00] "=&v"(z00), [n0] "=&s"(n0), [t] "=&s"(t)
+                     : [w0] "s"(w[0]), [i0] "i"(I0), [a0] "v"(a[0]), [b0] "v"(b[0])
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccK<1, 2> {
+    template <int I0, int O1>
+    __device__ __forceinline__ static void run(const uint32_t (&w)[1], const uint32_t (&a)[2],
+                                               const float (&b)[2]) {
+        float z00, z01;
+        uint32_t n0, t;
+        asm volatile(AFMM_ONE_ROW(AFMM_X2(AFMM_RD0), AFMM_X2(AFMM_AD0), AFMM_X2(AFMM_WR0))
+                     : [z00] "=&v"(z00), [z01] "=&v"(z01), [n0] "=&s"(n0), [t] "=&s"(t)
+                     : [w0] "s"(w[0]), [i0] "i"(I0), [a0] "v"(a[0]), [a1] "v"(a[1]),
+                       [b0] "v"(b[0]), [b1] "v"(b[1])
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccK<1, 4> {
+    template <int I0, int O1>
+    __device__ __forceinline__ static void run(const uint32_t (&w)[1], const uint32_t (&a)[4],
+                                               const float (&b)[4]) {
+        float z00, z01, z02, z03;
+        uint32_t n0, t;
+        asm volatile(AFMM_ONE_ROW(AFMM_X4(AFMM_RD0), AFMM_X4(AFMM_AD0), AFMM_X4(AFMM_WR0))
+                     : [z00] "=&v"(z00), [z01] "=&v"(z01), [z02] "=&v"(z02), [z03] "=&v"(z03),
+                       [n0] "=&s"(n0), [t] "=&s"(t)
+                     : [w0] "s"(w[0]), [i0] "i"(I0), [a0] "v"(a[0]), [a1] "v"(a[1]),
+                       [a2] "v"(a[2]), [a3] "v"(a[3]), [b0] "v"(b[0]), [b1] "v"(b[1]),
+                       [b2] "v"(b[2]), [b3] "v"(b[3])
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccK<2, 1> {
+    template <int I0, int O1>
+    __device__ __forceinline__ static void run(const uint32_t (&w)[2], const uint32_t (&a)[1],
+                                               const float (&b)[1]) {
+        float z00, z10;
+        uint32_t n0, n1, t;
+        asm volatile(AFMM_TWO_ROWS("1", AFMM_X1(AFMM_RD0), AFMM_X1(AFMM_RD1), AFMM_X1(AFMM_AD0),
+                                   AFMM_X1(AFMM_AD1), AFMM_X1(AFMM_WR0), AFMM_X1(AFMM_WR1))
+                     : [z00] "=&v"(z00), [z10] "=&v"(z10), [n0] "=&s"(n0), [n1] "=&s"(n1),
+                       [t] "=&s"(t)
+                     : [w0] "s"(w[0]), [w1] "s"(w[1]), [i0] "i"(I0), [i1] "i"(I0), [o1] "i"(O1),
+                       [a0] "v"(a[0]), [b0] "v"(b[0])
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccK<2, 2> {
+    template <int I0, int O1>
+    __device__ __forceinline__ static void run(const uint32_t (&w)[2], const uint32_t (&a)[2],
+                                               const float (&b)[2]) {
+        float z00, z01, z10, z11;
+        uint32_t n0, n1, t;
+        asm volatile(AFMM_TWO_ROWS("2", AFMM_X2(AFMM_RD0), AFMM_X2(AFMM_RD1), AFMM_X2(AFMM_AD0),
+                                   AFMM_X2(AFMM_AD1), AFMM_X2(AFMM_WR0), AFMM_X2(AFMM_WR1))
+                     : [z00] "=&v"(z00), [z01] "=&v"(z01), [z10] "=&v"(z10), [z11] "=&v"(z11),
+                       [n0] "=&s"(n0), [n1] "=&s"(n1), [t] "=&s"(t)
+                     : [w0] "s"(w[0]), [w1] "s"(w[1]), [i0] "i"(I0), [i1] "i"(I0), [o1] "i"(O1),
+                       [a0] "v"(a[0]), [a1] "v"(a[1]), [b0] "v"(b[0]), [b1] "v"(b[1])
+                     : "scc", "memory");
+    }
+};
+template <>
+struct AccK<2, 4> {
+    template <int I0, int O1>
+    __device__ __forceinline__ static void run(const uint32_t (&w)[2], const uint32_t (&a)[4],
+                                               const float (&b)[4]) {
+        float z00, z01, z02, z03, z10, z11, z12, z13;
+        uint32_t n0, n1, t;
+        asm volatile(AFMM_TWO_ROWS("4", AFMM_X4(AFMM_RD0), AFMM_X4(AFMM_RD1), AFMM_X4(AFMM_AD0),
+                                   AFMM_X4(AFMM_AD1), AFMM_X4(AFMM_WR0), AFMM_X4(AFMM_WR1))
+                     : [z00] "=&v"(z00), [z01] "=&v"(z01), [z02] "=&v"(z02), [z03] "=&v"(z03),
+                       [z10] "=&v"(z10), [z11] "=&v"(z11), [z12] "=&v"(z12), [z13] "=&v"(z13),
+                       [n0] "=&s"(n0), [n1] "=&s"(n1), [t] "=&s"(t)
+                     : [w0] "s"(w[0]), [w1] "s"(w[1]), [i0] "i"(I0), [i1] "i"(I0), [o1] "i"(O1),
+                       [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]), [a3] "v"(a[3]),
+                       [b0] "v"(b[0]), [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3])
+                     : "scc", "memory");
+    }
+};
+#undef AFMM_LOOP
+#undef AFMM_ONE_ROW
+#undef AFMM_TWO_ROWS
+#undef AFMM_RD0
+#undef AFMM_RD1
+#undef AFMM_AD0
+#undef AFMM_AD1
+#undef AFMM_WR0
+#undef AFMM_WR1
+#undef AFMM_X1
+#undef AFMM_X2
+#undef AFMM_X4
+
+// The 32-bit word of a row's count bytes that holds byte kk.
+template <int KP>
+__device__ __forceinline__ uint32_t count_word(const SparseCounts<KP>& c, int kk) {
+    if constexpr (KP == 4) {
+        return c.lo;
+    } else if constexpr (KP == 8) {
+        return (uint32_t)(c.lo >> (32 * (kk >> 2)));
+    } else {
+        return (uint32_t)((kk < 8 ? c.lo : c.hi) >> (32 * ((kk >> 2) & 1)));
+    }
+}
+
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1, each inlined.
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// One chunk of 64*E slots of the segment of k0 + kk, slot q of lane l being
+// entry ch_ + 64 q + l ({base bits, byte offset of its column in an LDS row};
+// a slot without a base holds +0.0 on the lane's sink column, so every lane
+// runs every slot).  Each of the wave's rows with a non-zero count reads its
+// E Z elements from LDS, adds each slot's base `rep` times (the E chains side
+// by side) and writes them back; the reads of all rows go out before the
+// first addition.
+#define AFMM_ACC_CHUNK(ev_)                                                                    \
     {                                                                                          \
-        int col_[T::E];                                                                        \
+        uint32_t ad_[T::E];                                                                    \
         float b_[T::E];                                                                        \
         _Pragma("unroll") for (int q = 0; q < T::E; ++q) {                                     \
-            const bool ok_ = (ch_) + q * kWave + lane < len_;                                  \
-            col_[q] = ok_ ? (int)(ev_)[q][1] : T::CT + lane;                                   \
-            b_[q] = ok_ ? __uint_as_float((ev_)[q][0]) : 0.0f;                                 \
+            ad_[q] = arow_a + (ev_)[q][1];                                                     \
+            b_[q] = __uint_as_float((ev_)[q][0]);                                              \
         }                                                                                      \
-        float z_[R][T::E];                                                                     \
-        _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
-            if (rep_[r] == 0) continue;                                                        \
-            _Pragma("unroll") for (int q = 0; q < T::E; ++q) z_[r][q] =                        \
-                arow[r * T::STRIDE + col_[q]];                                                 \
-        }                                                                                      \
-        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);                                                \
-        _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
-            uint32_t n_ = rep_[r];                                                             \
-            if (n_ == 0) continue;                                                             \
-            float zz_[T::E];                                                                   \
-            _Pragma("unroll") for (int q = 0; q < T::E; ++q) zz_[q] = z_[r][q];                \
-            if (U == 4) {                                                                      \
-                /* bits of the count: 1, 2 and 4 additions under scalar bit */                 \
-                /* tests, then runs of 8 */                                                    \
-                if (n_ & 1u) AFMM_ACC_ADD(1);                                                  \
-                if (n_ & 2u) AFMM_ACC_ADD(2);                                                  \
-                if (n_ & 4u) AFMM_ACC_ADD(4);                                                  \
-                for (n_ >>= 3; n_ != 0; --n_) AFMM_ACC_ADD(8);                                 \
-            } else if (U == 2) {                                                               \
-                if (n_ & 1u) AFMM_ACC_ADD(1);                                                  \
-                for (n_ >>= 1; n_ != 0; --n_) AFMM_ACC_ADD(2);                                 \
-            } else {                                                                           \
-                do {                                                                           \
-                    AFMM_ACC_ADD(1);                                                           \
-                } while (--n_ != 0);                                                           \
+        if constexpr (R <= 2 || (R == 4 && T::E <= 2)) {                                      \
+            float z_[R < 2 ? 2 : R][T::E];                                                     \
+            AccAsm<T::E, R>::template read<T::STRIDE * 4>(z_, rep_, ad_);                      \
+            AccRow<T::E>::template run<0>(z_[0], b_, rep_[0], ad_);                            \
+            if constexpr (R >= 2) AccRow<T::E>::template run<T::STRIDE * 4>(z_[1], b_, rep_[1], ad_); \
+            if constexpr (R == 4) {                                                            \
+                AccRow<T::E>::template run<2 * T::STRIDE * 4>(z_[2], b_, rep_[2], ad_);        \
+                AccRow<T::E>::template run<3 * T::STRIDE * 4>(z_[3], b_, rep_[3], ad_);        \
             }                                                                                  \
-            _Pragma("unroll") for (int q = 0; q < T::E; ++q) arow[r * T::STRIDE + col_[q]] =   \
-                zz_[q];                                                                        \
+        } else {                                                                               \
+            float z_[R][T::E];                                                                 \
+            _Pragma("unroll") for (int r = 0; r < R; ++r) {                                    \
+                if (rep_[r] == 0) continue;                                                    \
+                _Pragma("unroll") for (int q = 0; q < T::E; ++q) z_[r][q] =                    \
+                    *lds_at(ad_[q] + r * T::STRIDE * 4);                                       \
+            }                                                                                  \
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);                                            \
+            _Pragma("unroll") for (int r = 0; r < R; ++r) {                                    \
+                if (rep_[r] == 0) continue;                                                    \
+                add_times<T::E>(z_[r], b_, rep_[r]);                                           \
+                _Pragma("unroll") for (int q = 0; q < T::E; ++q)                               \
+                    *lds_at(ad_[q] + r * T::STRIDE * 4) = z_[r][q];                            \
+            }                                                                                  \
         }                                                                                      \
-    }
-
-// `times` more repetitions of every slot's base (slots interleaved, each
-// slot's own additions in order)
-#define AFMM_ACC_ADD(times)                                                                    \
-    {                                                                                          \
-        _Pragma("unroll") for (int t_ = 0; t_ < (times); ++t_)                                 \
-            _Pragma("unroll") for (int q = 0; q < T::E; ++q) zz_[q] = zz_[q] + b_[q];          \
     }
 
 // The additions of k0 + kk for the wave's R rows: the prefetched first 64*E
-// entries, then (longer segments) the rest, 64*E at a time.
+// slots, then (longer segments) the rest, 64*E at a time.  Segment lengths are
+// 0 or multiples of 64*E.
 #define AFMM_ACC_K(kk)                                                                         \
+    if constexpr (!ESC && R <= 2) {                                                            \
+        const int len_ = Lc[kk];                                                               \
+        if (len_ != 0) {                                                                       \
+            uint32_t w_[R], ad_[T::E];                                                         \
+            float b_[T::E];                                                                    \
+            _Pragma("unroll") for (int r = 0; r < R; ++r) w_[r] = count_word<KP>(cw[r], kk);   \
+            _Pragma("unroll") for (int q = 0; q < T::E; ++q) {                                 \
+                ad_[q] = arow_a + ec[kk][q][1];                                                \
+                b_[q] = __uint_as_float(ec[kk][q][0]);                                         \
+            }                                                                                  \
+            AccK<R, T::E>::template run<((kk) % 4) * 8 | (8 << 16), T::STRIDE * 4>(w_, ad_, b_); \
+            if (__builtin_expect(len_ > kWave * T::E, 0)) {                                    \
+                uint32_t rep_[R];                                                              \
+                _Pragma("unroll") for (int r = 0; r < R; ++r) rep_[r] = cw[r].byte(kk);        \
+                AFMM_ACC_MORE(kk)                                                              \
+            }                                                                                  \
+        }                                                                                      \
+    } else {                                                                                   \
+        AFMM_ACC_K_ANY(kk);                                                                    \
+    }
+
+// The slots of k0 + kk past the first 64*E, 64*E at a time.
+#define AFMM_ACC_MORE(kk)                                                                      \
+    for (int ch2_ = kWave * T::E; ch2_ < len_; ch2_ += kWave * T::E) {                         \
+        u32x2_t e2_[T::E];                                                                     \
+        _Pragma("unroll") for (int q = 0; q < T::E; ++q) e2_[q] =                              \
+            __builtin_amdgcn_raw_buffer_load_b64(                                              \
+                ers, (uint32_t)(((k0 + (kk)) * T::CT + ch2_ + q * kWave + lane) * 8), 0,       \
+                0); /* ch2_ + q * 64 + lane < CT */                                            \
+        AFMM_ACC_CHUNK(e2_)                                                                    \
+    }
+
+// Any k: escaped counts, waves of more than two rows.
+#define AFMM_ACC_K_ANY(kk)                                                                     \
     do {                                                                                       \
         const int len_ = Lc[kk];                                                               \
         if (len_ == 0) break;                                                                  \
@@ -173,18 +640,11 @@ struct AccTile {
             any_ |= v_;                                                                        \
         }                                                                                      \
         if (any_ == 0) break;                                                                  \
-        AFMM_ACC_CHUNK(ec[kk], 0)                                                              \
-        for (int ch2_ = kWave * T::E; ch2_ < len_; ch2_ += kWave * T::E) {                     \
-            u32x2_t e2_[T::E];                                                                 \
-            _Pragma("unroll") for (int q = 0; q < T::E; ++q) e2_[q] =                          \
-                __builtin_amdgcn_raw_buffer_load_b64(                                          \
-                    ers, (uint32_t)(((k0 + (kk)) * T::CT + ch2_ + q * kWave + lane) * 8), 0,   \
-                    0); /* ch2_ + q * 64 + lane < CT */                                        \
-            AFMM_ACC_CHUNK(e2_, ch2_)                                                          \
-        }                                                                                      \
+        AFMM_ACC_CHUNK(ec[kk])                                                                 \
+        AFMM_ACC_MORE(kk)                                                                      \
     } while (0)
 
-template <int R, int C, int W, int U, int KP, bool TRANS_OUT, bool ESC>
+template <int R, int C, int W, int KP, bool TRANS_OUT, bool ESC>
 __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
                                              const uint8_t* __restrict__ P8, int64_t ldp,
                                              const int32_t* __restrict__ P32, int64_t p32_sr,
@@ -198,7 +658,8 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int rw0 = r0 + wave * R;
     const int c0 = band * T::CT;
-    float* arow = lds + wave * R * T::STRIDE;
+    // LDS byte address of the wave's first row (entries hold byte offsets in a row)
+    const uint32_t arow_a = lds_address(lds + wave * R * T::STRIDE);
 
     // Z starts at +0.0 (the sink columns too: they only ever receive +0.0)
     float4* l4 = reinterpret_cast<float4*>(lds);
@@ -270,8 +731,10 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
 #pragma unroll
             for (int r = 0; r < R; ++r) cf[r].fetch(crs, (uint32_t)((rw0 + r) * ldp + k1));
         }
-#pragma unroll
-        for (int kk = 0; kk < KP; ++kk) AFMM_ACC_K(kk);
+        static_for<KP>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int kk = decltype(kc)::value;
+            AFMM_ACC_K(kk);
+        });
         // the next panel's loads have had this whole panel to land; waiting for
         // them here leaves nothing pending at the top of the loop, so the uses
         // of the entries there need no wait of their own
@@ -305,10 +768,11 @@ __device__ __forceinline__ void rep_acc_tile(int n_r, int n_c, int n_k,
     }
 }
 #undef AFMM_ACC_K
-#undef AFMM_ACC_ADD
+#undef AFMM_ACC_K_ANY
+#undef AFMM_ACC_MORE
 #undef AFMM_ACC_CHUNK
 
-template <int R, int C, int W, int U, int KP, bool TRANS_OUT>
+template <int R, int C, int W, int KP, bool TRANS_OUT>
 __global__ __launch_bounds__(W * kWave) void rep_acc_kernel(
     int n_r, int n_c, int n_k, const uint8_t* __restrict__ P8, int64_t ldp,
     const int32_t* __restrict__ P32, int64_t p32_sr, int64_t p32_sk, const uint2* __restrict__ ent,
@@ -321,16 +785,16 @@ __global__ __launch_bounds__(W * kWave) void rep_acc_kernel(
     const int t = xcd_remap(blockIdx.x, n_tiles);
     const int band = t / n_row_blocks, rb = t - band * n_row_blocks;
     if (*esc)
-        rep_acc_tile<R, C, W, U, KP, TRANS_OUT, true>(n_r, n_c, n_k, P8, ldp, P32, p32_sr, p32_sk,
+        rep_acc_tile<R, C, W, KP, TRANS_OUT, true>(n_r, n_c, n_k, P8, ldp, P32, p32_sr, p32_sk,
                                                       ent, lens, n_k_pad, Z, z_sr, z_sc,
                                                       rb * T::TM, band, lds);
     else
-        rep_acc_tile<R, C, W, U, KP, TRANS_OUT, false>(n_r, n_c, n_k, P8, ldp, P32, p32_sr,
+        rep_acc_tile<R, C, W, KP, TRANS_OUT, false>(n_r, n_c, n_k, P8, ldp, P32, p32_sr,
                                                        p32_sk, ent, lens, n_k_pad, Z, z_sr, z_sc,
                                                        rb * T::TM, band, lds);
 }
 
-template <int R, int C, int W, int U, int KP>
+template <int R, int C, int W, int KP>
 hipError_t launch_acc(const StrictArgs& a, const AccLists& L, hipStream_t s) {
     using T = AccTile<R, C, W, KP>;
     if (!rep_acc_usable(a, C)) return hipErrorInvalidValue;
@@ -338,18 +802,19 @@ hipError_t launch_acc(const StrictArgs& a, const AccLists& L, hipStream_t s) {
     const int n_tiles = n_row_blocks * ((a.n_c + T::CT - 1) / T::CT);
     dim3 grid(n_tiles), block(W * kWave);
     if (a.trans_out)
-        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, KP, true>), grid, block, 0, s, a.n_r,
+        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, KP, true>), grid, block, 0, s, a.n_r,
                            a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
                            L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     else
-        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, U, KP, false>), grid, block, 0, s, a.n_r,
+        hipLaunchKernelGGL((rep_acc_kernel<R, C, W, KP, false>), grid, block, 0, s, a.n_r,
                            a.n_c, a.n_k, a.P8, a.ldp, a.P32, a.p32_sr, a.p32_sk, L.ent, L.lens,
                            L.n_k_pad, a.Z, a.z_sr, a.z_sc, a.esc, n_row_blocks, n_tiles, a.gate);
     return hipGetLastError();
 }
 
 // (R, C, W, U, KP): TM = W*R rows x CT = 64*C columns of Z in LDS per block;
-// each lane takes max(1, C/16) entries of a k's segment
+// each lane takes max(1, C/16) entries of a k's segment.  U is accepted and
+// ignored: the repetitions run in a counted scalar loop (add_times).
 #define AFMM_ACC_CONFIGS(X) \
     X(4, 16, 8, 1, 16)      \
     X(4, 16, 8, 2, 16)      \
@@ -363,7 +828,18 @@ hipError_t launch_acc(const StrictArgs& a, const AccLists& L, hipStream_t s) {
     X(2, 32, 8, 2, 8)       \
     X(1, 32, 16, 2, 8)      \
     X(1, 64, 8, 2, 8)       \
-    X(1, 64, 8, 1, 8)
+    X(1, 64, 8, 1, 8)       \
+    X(2, 32, 8, 1, 16)      \
+    X(1, 16, 16, 1, 16)     \
+    X(2, 16, 8, 1, 16)      \
+    X(1, 16, 8, 1, 8)       \
+    X(1, 16, 16, 1, 8)      \
+    X(1, 32, 8, 1, 8)       \
+    X(2, 16, 8, 1, 8)       \
+    X(1, 16, 8, 1, 16)      \
+    X(4, 16, 4, 1, 16)      \
+    X(4, 16, 4, 1, 8)       \
+    X(4, 32, 4, 1, 8)
 
 bool rep_acc_usable(const StrictArgs& a, int C) {
     // buffer-resource byte offsets of one band's segments and of the count
@@ -384,7 +860,7 @@ bool rep_acc_supported(int R, int C, int W, int U, int KP) {
 hipError_t launch_rep_acc(const StrictArgs& a, const AccLists& L, int R, int C, int W, int U,
                           int KP, hipStream_t s) {
 #define AFMM_CASE(r, c, w, u, kp) \
-    if (R == r && C == c && W == w && U == u && KP == kp) return launch_acc<r, c, w, u, kp>(a, L, s);
+    if (R == r && C == c && W == w && U == u && KP == kp) return launch_acc<r, c, w, kp>(a, L, s);
     AFMM_ACC_CONFIGS(AFMM_CASE)
 #undef AFMM_CASE
     return hipErrorInvalidValue;

@@ -4,7 +4,8 @@ The form lists each k's non-zero bases per band of lane columns and keeps the Z
 block in LDS; it must give the oracle's bits exactly like every other form.  Cases
 cover ragged sizes, real-factor densities from 2 % (C5-like) to 100 % (segments
 longer than 64 entries per lane slot set, walked in several chunks; lanes with
-one, two and four slots), -0.0 bases (skipped like +0.0),
+one, two and four slots), bases piled into few residues modulo 64 of the lane
+axis (slots handed between lanes), -0.0 bases (skipped like +0.0),
 counts of 255 and more (escape path), an all-zero real factor, and sampled rows of
 the n=16384 case-A workload.
 """
@@ -20,7 +21,11 @@ ACC = [(4, 4, 16, 8, 1, 16), (4, 4, 16, 8, 2, 16), (4, 4, 16, 8, 4, 16), (4, 2, 
        (4, 2, 16, 16, 2, 16), (4, 2, 16, 16, 4, 16), (4, 4, 8, 16, 1, 16), (4, 8, 8, 8, 1, 16),
        (4, 4, 4, 8, 1, 16),
        # two and four entries per lane (bands of 2048 and 4096 columns, 8-k panels)
-       (4, 2, 32, 8, 2, 8), (4, 1, 32, 16, 2, 8), (4, 1, 64, 8, 2, 8), (4, 1, 64, 8, 1, 8)]
+       (4, 2, 32, 8, 2, 8), (4, 1, 32, 16, 2, 8), (4, 1, 64, 8, 2, 8), (4, 1, 64, 8, 1, 8),
+       # 16-k panels, several blocks per CU; waves of one, two and four rows
+       (4, 2, 32, 8, 1, 16), (4, 1, 16, 16, 1, 16), (4, 2, 16, 8, 1, 16), (4, 1, 16, 8, 1, 8),
+       (4, 1, 16, 16, 1, 8), (4, 1, 32, 8, 1, 8), (4, 2, 16, 8, 1, 8), (4, 1, 16, 8, 1, 16),
+       (4, 4, 16, 4, 1, 16), (4, 4, 16, 4, 1, 8), (4, 4, 32, 4, 1, 8)]
 
 
 @pytest.fixture(scope="module")
@@ -74,6 +79,30 @@ def test_acc_sizes_and_densities(dev, case, n):
     for d_real in (0.02, 0.3, 1.0):
         X, Y = _inputs(case, n, 900 + n + int(100 * d_real), d_real)
         _check_all(dev, case, X, Y)
+
+
+@pytest.mark.parametrize("case", ["A", "B"])
+@pytest.mark.parametrize("pattern", ["one_residue", "two_residues", "clustered"])
+def test_acc_uneven_bank_classes(dev, case, pattern):
+    """Non-zero bases piled into few residues modulo 64 of the lane axis (i in
+    case A, j in case B): the slots of a k take each lane's own columns first
+    and hand the rest to other lanes' free slots; every base must still be
+    added exactly once per k."""
+    n = 700
+    X, Y = _inputs(case, n, 404 + len(pattern), 1.0)
+    real = X if case == "A" else Y
+    idx = np.arange(n)
+    if pattern == "one_residue":
+        keep = idx % 64 == 5
+    elif pattern == "two_residues":
+        keep = (idx % 64 == 5) | (idx % 64 == 40)
+    else:
+        keep = (idx >= 100) & (idx < 100 + 150)  # one run: every residue, two or three each
+    if case == "A":
+        real[~keep, :] = 0  # lanes run over the rows of X
+    else:
+        real[:, ~keep] = 0  # lanes run over the columns of Y
+    _check_all(dev, case, X, Y)
 
 
 @pytest.mark.parametrize("case", ["A", "B"])

@@ -105,15 +105,18 @@ def test_rows_quadratic_regime_sampled(dev, case):
 
 @pytest.mark.parametrize("case", ["A", "B"])
 def test_suggested_configuration(dev, case):
-    """afmm_suggest_config: row lists when d_real * d_int * n <= 32 (case A) or 42
+    """afmm_suggest_config: row lists when d_real * d_int * n <= 32 (case A) or 64
     (case B), compacted bases when only the real factor is very sparse (<= 6 %),
     the size-keyed choice otherwise and below n = 1024; the suggested
     configuration gives the default's bits.  (Positive counts are 6/7 of the
     integer mask here.)"""
     afmm = _afmm()
     n = 2048
-    for d_real, d_int, mapping in ((0.1, 0.1, 7), (0.05, 0.7, 4), (0.1, 0.5, None),
+    for d_real, d_int, mapping in ((0.1, 0.1, 7), (0.05, 0.9, 4), (0.1, 0.5, None),
                                    (0.9, 0.3, None),
+                                   # d_real * d_int * n = 61: compacted bases in case A,
+                                   # row lists in case B
+                                   (0.05, 0.7, 7 if case == "B" else 4),
                                    # d_real * d_int * n = 37: row lists in case B only
                                    (0.12, 0.175, 7 if case == "B" else None)):
         X, Y = _inputs(case, n, 40 + int(100 * d_real), d_real, d_int)
@@ -137,7 +140,7 @@ PLAIN_REGIMES = [(0.6, 0.7, "dense"), (0.05, 0.95, 4), (0.03, 0.05, 7)]
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
-@pytest.mark.parametrize("n", [1031, 2085])
+@pytest.mark.parametrize("n", [1543, 2085])
 @pytest.mark.parametrize("regime", PLAIN_REGIMES, ids=lambda r: str(r[2]))
 def test_plain_call_chooses_form_bitexact(dev, case, n, regime):
     """afmm_multiply_caseA / caseB without a configuration, on ragged sizes in
