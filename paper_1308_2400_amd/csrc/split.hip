@@ -26,7 +26,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kTI = 256;  // block rows on the integer side
 constexpr int kTS = 128;  // block rows on the split (three-term) side
-constexpr int kGK = 32;   // K per LDS stage: four 16-byte chunks per row
 
 int split_real_rows_pad(int n) { return (int)round_up(n, kTS); }
 int split_int_rows_pad(int n) { return (int)round_up(n, kTI); }
@@ -167,16 +166,31 @@ hipError_t launch_split_prep(bool case_a, const SplitPrepArgs& a, hipStream_t s)
 // that belongs there), two stages ahead of the MFMAs, with one barrier per
 // stage.
 constexpr int kGemmWaves = 8;
-constexpr int kPlaneI = kTI * kGK;                    // bf16 per I tile
-constexpr int kPlaneS = kTS * kGK;                    // bf16 per S tile
-constexpr int kStage = kPlaneI + 3 * kPlaneS;         // 40 KB
-constexpr int kStages = 3;                            // LDS stages in flight
-constexpr int kGroups = kStage / (16 * kGK);          // 1 KB row groups per stage (40)
-constexpr int kGroupsPerWave = kGroups / kGemmWaves;  // 5
-static_assert(kTI == 2 * 128 && kTS == 4 * 32, "wave grid 2 x 4");
-static_assert(kTI / 16 == 2 * kGemmWaves && kTS / 16 == kGemmWaves, "row groups per wave");
 
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+// Stage geometry for GK K values per LDS stage (32: four 16-byte chunks per
+// row, three stages in flight; 64: eight chunks, two stages).  A 1 KB direct
+// load fills RPG rows of one plane (a row group).
+template <int GK>
+struct GemmStage {
+    static constexpr int CH = GK / 8;                     // 16-byte chunks per row
+    static constexpr int PLANE_I = kTI * GK;              // bf16 per I tile
+    static constexpr int PLANE_S = kTS * GK;              // bf16 per S tile
+    static constexpr int STAGE = PLANE_I + 3 * PLANE_S;   // bf16 per stage
+    static constexpr int STAGES = GK == 32 ? 3 : 2;       // stages in LDS
+    static constexpr int RPG = 512 / GK;                  // rows per 1 KB group
+    static constexpr int IG = kTI / RPG / kGemmWaves;     // I groups per wave
+    static constexpr int SG = kTS / RPG / kGemmWaves;     // S groups per wave and plane
+    static constexpr int GPW = IG + 3 * SG;               // loads per wave and stage
+    static_assert(STAGES * STAGE * 2 <= 160 * 1024, "stages must fit in LDS");
+    static_assert(IG >= 1 && SG >= 1, "every wave loads whole groups");
+    // chunk slot of chunk q in row r: any 16 consecutive rows read one chunk
+    // each from 16 different 16-byte bank groups
+    __device__ __forceinline__ static int swz(int r) {
+        if constexpr (GK == 32) return ((r >> 1) ^ (r >> 3)) & 3;
+        else return (r >> 1) & 7;
+    }
+};
+static_assert(kTI == 2 * 128 && kTS == 4 * 32, "wave grid 2 x 4");
 
 // s_waitcnt immediate: vector memory count <= v (bits 3:0 and 15:14), LDS and
 // scalar memory count not waited for (bits 11:8), export count not waited for
@@ -197,12 +211,22 @@ __device__ __forceinline__ void gemm_tile_coords(int t, int tiles_i, int tiles_s
     ts = r / gi;
 }
 
-template <bool CASE_A>
+// 16 bytes per lane from buffer offset voff + koff straight into LDS at gd
+// (lane order).  A plain device function: inside the kernel template the host
+// pass would not instantiate the builtin, and the launch would find no kernel.
+__device__ __forceinline__ void load_lds16(__amdgpu_buffer_rsrc_t rs, uint16_t* gd, uint32_t voff,
+                                           uint32_t koff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)gd, 16,
+                                             voff, koff, 0, 0);
+}
+
+template <bool CASE_A, int GK>
 __global__ __launch_bounds__(kGemmWaves * 64, 1) void gemm_bf16x3_kernel(
     int M, int N, const uint16_t* __restrict__ I, const uint16_t* __restrict__ S0,
     const uint16_t* __restrict__ S1, const uint16_t* __restrict__ S2, int64_t ld,
     float* __restrict__ Z, int64_t ldz, int tiles_i, int tiles_s) {
-    __shared__ __attribute__((aligned(1024))) uint16_t lds[kStages * kStage];
+    using G = GemmStage<GK>;
+    __shared__ __attribute__((aligned(1024))) uint16_t lds[G::STAGES * G::STAGE];
 
     int ti, ts;
     gemm_tile_coords(xcd_remap(blockIdx.x, tiles_i * tiles_s), tiles_i, tiles_s, ti, ts);
@@ -226,36 +250,36 @@ __global__ __launch_bounds__(kGemmWaves * 64, 1) void gemm_bf16x3_kernel(
                                           (int)(kTS * row_bytes), 0x00020000)};
     const __amdgpu_buffer_rsrc_t rZero =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(I), (short)0, 0, 0x00020000);
-    const int n_st = (int)(ld / kGK);  // ld is a multiple of 64: an even count >= 2
+    const int n_st = (int)(ld / GK);  // ld is a multiple of 64
 
-    // This wave's row groups of a stage, 16 rows of one plane each: j = 0, 1
-    // the I tile's groups 8 j + wave, j = 2, 3, 4 group `wave` of S tile j - 2.
-    // Lane L fetches row 16 group + L / 4, chunk (L % 4) ^ swz(row) (swz
-    // depends on the row modulo 32).
-    uint32_t voff[kGroupsPerWave];
+    // This wave's row groups of a stage: the I tile's groups 8 j + wave
+    // (j < IG), then of each S tile the groups 8 j + wave (j < SG).  Lane L
+    // fetches row RPG group + L / CH, chunk (L % CH) ^ swz(row), which the
+    // direct load puts at slot L % CH.
+    uint32_t voff[G::GPW];
 #pragma unroll
-    for (int j = 0; j < kGroupsPerWave; ++j) {
-        const int grp = (j < 2 ? 8 * j : 0) + wave;
-        const int row = grp * 16 + (lane >> 2);
-        const int chunk = (lane & 3) ^ swz(row);
+    for (int j = 0; j < G::GPW; ++j) {
+        const int grp = (j < G::IG ? j : (j - G::IG) % G::SG) * kGemmWaves + wave;
+        const int row = grp * G::RPG + lane / G::CH;
+        const int chunk = (lane % G::CH) ^ G::swz(row);
         voff[j] = (uint32_t)row * row_bytes + (uint32_t)chunk * 16u;
     }
-    // Stage st (K 32 st .. +31) into buffer st % kStages.  Past the last stage
+    // Stage st (K GK st .. +GK-1) into buffer st % STAGES.  Past the last stage
     // the resource covers no bytes: the loads return zeros into a buffer nobody
     // reads any more, which keeps the loop free of branches.
     auto issue = [&](int st) {
-        uint16_t* dst = lds + (st % kStages) * kStage;
-        const uint32_t koff = (uint32_t)st * (kGK * 2);
+        uint16_t* dst = lds + (st % G::STAGES) * G::STAGE;
+        const uint32_t koff = (uint32_t)st * (GK * 2);
         const bool live = st < n_st;
 #pragma unroll
-        for (int j = 0; j < kGroupsPerWave; ++j) {
-            const int plane = j < 2 ? -1 : j - 2;
-            const int grp = (j < 2 ? 8 * j : 0) + wave;
+        for (int j = 0; j < G::GPW; ++j) {
+            const int plane = j < G::IG ? -1 : (j - G::IG) / G::SG;
+            const int grp = (j < G::IG ? j : (j - G::IG) % G::SG) * kGemmWaves + wave;
             __amdgpu_buffer_rsrc_t rs = plane < 0 ? rI : rS[plane];
             if (!live) rs = rZero;
-            uint16_t* gd = dst + (plane < 0 ? 0 : kPlaneI + plane * kPlaneS) + grp * 16 * kGK;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rs, (__attribute__((address_space(3))) void*)gd, 16, voff[j], koff, 0, 0);
+            uint16_t* gd = dst + (plane < 0 ? 0 : G::PLANE_I + plane * G::PLANE_S) +
+                           grp * G::RPG * GK;
+            load_lds16(rs, gd, voff[j], koff);
         }
     };
 
@@ -269,19 +293,20 @@ __global__ __launch_bounds__(kGemmWaves * 64, 1) void gemm_bf16x3_kernel(
         }
 
     // Fragment rows are a multiple of 32 plus fr, and swz(32 a + fr) == swz(fr):
-    // one swizzled chunk offset per lane and K step.
+    // one swizzled chunk offset per lane and K step (chunks 2 s and 2 s + 1).
     const int fr = lane & 31, fq = lane >> 5;
-    const int fo0 = fr * kGK + ((fq ^ swz(fr)) * 8);        // K step 0: chunks 0, 1
-    const int fo1 = fr * kGK + (((fq + 2) ^ swz(fr)) * 8);  // K step 1: chunks 2, 3
+    int fo[GK / 16];
+#pragma unroll
+    for (int k = 0; k < GK / 16; ++k) fo[k] = fr * GK + (((2 * k + fq) ^ G::swz(fr)) * 8);
 #define AFMM_FRAG(cur, off) (*reinterpret_cast<const bf16x8*>((cur) + (off)))
 #define AFMM_MFMA(acc, a, b) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     // The fragments of one 16-wide K step from the stage at cur, and its MFMAs:
     // hi into its own set, lo then mid into the second.
 #define AFMM_READ(fi, fs, cur, fo)                                                        \
     _Pragma("unroll") for (int i = 0; i < 4; ++i)                                         \
-        fi[i] = AFMM_FRAG(cur, (wi + 32 * i) * kGK + (fo));                               \
+        fi[i] = AFMM_FRAG(cur, (wi + 32 * i) * GK + (fo));                                \
     _Pragma("unroll") for (int t = 0; t < 3; ++t)                                         \
-        fs[t] = AFMM_FRAG(cur, kPlaneI + t * kPlaneS + ws * kGK + (fo));
+        fs[t] = AFMM_FRAG(cur, G::PLANE_I + t * G::PLANE_S + ws * GK + (fo));
 #define AFMM_STEP(fi, fs)                                                                 \
     _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                       \
         if (CASE_A) { AFMM_MFMA(acc_hi[i], fs[0], fi[i]) }                                \
@@ -293,28 +318,31 @@ __global__ __launch_bounds__(kGemmWaves * 64, 1) void gemm_bf16x3_kernel(
         else { AFMM_MFMA(acc_lo[i], fi[i], fs[t]) }                                       \
     }
 
-    // Stages st + 1 and st + 2 are in flight while st is computed.  At the top
-    // of each stage a wave waits for its own loads of the stage, then the
-    // barrier: every wave's loads of it have landed, and every wave is done
-    // with the buffer the next issue overwrites.  (A plain barrier: the
-    // compiler's workgroup barrier would also wait for the loads still in
-    // flight for the next stage.)
-    issue(0);
-    issue(1);
+    // STAGES - 1 stages are in flight while one is computed.  At the top of
+    // each stage a wave waits for its own loads of the stage, then the barrier:
+    // every wave's loads of it have landed, and every wave is done with the
+    // buffer the next issue overwrites.  (A plain barrier: the compiler's
+    // workgroup barrier would also wait for the loads still in flight.)
+#pragma unroll
+    for (int st = 0; st < G::STAGES - 1; ++st) issue(st);
     for (int st = 0; st < n_st; ++st) {
-        __builtin_amdgcn_s_waitcnt(wait_vm(kGroupsPerWave));  // stage st landed
+        // loads issued after this stage's: those of the STAGES - 2 later stages
+        __builtin_amdgcn_s_waitcnt(wait_vm(G::GPW * (G::STAGES - 2)));
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        const uint16_t* cur = lds + (st % kStages) * kStage;
+        const uint16_t* cur = lds + (st % G::STAGES) * G::STAGE;
         // the compiler spreads the reads between the MFMAs (reading both steps'
         // fragments at once queues the LDS up behind eight waves: slower)
-        bf16x8 fi0[4], fs0[3], fi1[4], fs1[3];
-        AFMM_READ(fi0, fs0, cur, fo0)
-        issue(st + 2);
-        AFMM_READ(fi1, fs1, cur, fo1)
-        AFMM_STEP(fi0, fs0)
-        AFMM_STEP(fi1, fs1)
+#pragma unroll
+        for (int h = 0; h < GK / 32; ++h) {
+            bf16x8 fi0[4], fs0[3], fi1[4], fs1[3];
+            AFMM_READ(fi0, fs0, cur, fo[2 * h])
+            if (h == 0) issue(st + G::STAGES - 1);
+            AFMM_READ(fi1, fs1, cur, fo[2 * h + 1])
+            AFMM_STEP(fi0, fs0)
+            AFMM_STEP(fi1, fs1)
+        }
     }
     // the zero loads past the last stage must land before the block's LDS goes
     __builtin_amdgcn_s_waitcnt(wait_vm(0));
@@ -337,6 +365,9 @@ __global__ __launch_bounds__(kGemmWaves * 64, 1) void gemm_bf16x3_kernel(
         }
 }
 
+// K per stage of the GEMM the launcher runs
+constexpr int kGemmGK = 64;
+
 hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, const uint16_t* S0,
                               const uint16_t* S1, const uint16_t* S2, int64_t ld, float* Z,
                               int64_t ldz, hipStream_t s) {
@@ -346,11 +377,11 @@ hipError_t launch_gemm_bf16x3(bool case_a, int M, int N, const uint16_t* I, cons
     const int tiles_i = (rows_i + kTI - 1) / kTI, tiles_s = (rows_s + kTS - 1) / kTS;
     const int n_tiles = tiles_i * tiles_s;
     if (case_a)
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(n_tiles), dim3(kGemmWaves * 64), 0, s, M, N, I, S0,
-                           S1, S2, ld, Z, ldz, tiles_i, tiles_s);
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<true, kGemmGK>), dim3(n_tiles), dim3(kGemmWaves * 64),
+                           0, s, M, N, I, S0, S1, S2, ld, Z, ldz, tiles_i, tiles_s);
     else
-        hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(n_tiles), dim3(kGemmWaves * 64), 0, s, M, N, I, S0,
-                           S1, S2, ld, Z, ldz, tiles_i, tiles_s);
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<false, kGemmGK>), dim3(n_tiles), dim3(kGemmWaves * 64),
+                           0, s, M, N, I, S0, S1, S2, ld, Z, ldz, tiles_i, tiles_s);
     return hipGetLastError();
 }
 
