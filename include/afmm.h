@@ -344,6 +344,17 @@ afmm_status afmm_batched_plan_problem_adds(const afmm_plan *plan, uint64_t *d_ou
 /* Release the plan (synchronises the device first). */
 afmm_status afmm_batched_plan_destroy(afmm_plan *plan);
 
+/*
+ * Tile shapes of the persistent strict kernel, by problem size: a problem with
+ * n >= n_wide gets 8-row x 512-column tiles (the sparse-k body), n >= n_mid
+ * 8 x 256, smaller ones 8 x 64 (the LDS-panel body).  Built in: 512 and 128;
+ * the autotuner measures the batched workload over a grid of thresholds and
+ * stores the fastest pair in its table.  Applies to plans created after the
+ * call; every shape gives the same bits.  AFMM_ERR_INVALID_ARG unless
+ * 1 <= n_mid <= n_wide.
+ */
+afmm_status afmm_set_batch_shapes(int64_t n_wide, int64_t n_mid);
+
 /* One-shot convenience: create, launch on `stream`, wait, destroy. */
 afmm_status afmm_multiply_batched(const afmm_problem *problems, int32_t count, afmm_mode mode,
                                   hipStream_t stream);

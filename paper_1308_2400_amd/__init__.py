@@ -72,6 +72,7 @@ _SIGS = {
     "afmm_multiply_strict_config": ([_ci, _i64, _vp, _vp, _vp, ctypes.POINTER(afmm_config), _vp,
                                      _sz, _vp], _ci),
     "afmm_set_tuning": ([_i32, _vp, _vp, _vp, _vp], _ci),
+    "afmm_set_batch_shapes": ([_i64, _i64], _ci),
     "afmm_batched_plan_create": ([ctypes.POINTER(afmm_problem), _i32, _ci, ctypes.POINTER(_vp)], _ci),
     "afmm_batched_plan_launch": ([_vp, _vp], _ci),
     "afmm_batched_plan_problem_adds": ([_vp, _vp, _vp], _ci),
@@ -311,6 +312,12 @@ def set_tuning(entries):
     _check("set_tuning", _lib.afmm_set_tuning(k, cases, lo, hi, cfgs))
 
 
+def set_batch_shapes(n_wide=512, n_mid=128):
+    """Size thresholds of the batched kernel's tile shapes for plans created from
+    now on (see afmm_set_batch_shapes)."""
+    _check("set_batch_shapes", _lib.afmm_set_batch_shapes(int(n_wide), int(n_mid)))
+
+
 def load_tuning(path=None):
     """Load a tuning table written by the autotuner (JSON), if present."""
     import json
@@ -320,6 +327,9 @@ def load_tuning(path=None):
     with open(path) as f:
         d = json.load(f)
     set_tuning((e["case"], e["n_lo"], e["n_hi"], tuple(e["config"])) for e in d["entries"])
+    b = d.get("batch_shapes")
+    if b:
+        set_batch_shapes(b["n_wide"], b["n_mid"])
     return True
 
 

@@ -52,7 +52,14 @@ struct BatchProblem {
 // column per lane for the small ones (a 256-column tile would be mostly empty).
 __host__ __device__ inline int shape_R(int) { return 2; }
 __host__ __device__ inline int shape_C(int s) { return s == 0 ? 8 : (s == 1 ? 4 : 1); }
-inline int shape_for(int n) { return n >= 512 ? 0 : (n >= 128 ? 1 : 2); }
+// Size thresholds of the shapes (afmm_set_batch_shapes; the autotuner's
+// table): n >= g_n_wide takes shape 0, n >= g_n_mid shape 1, the rest shape 2.
+std::mutex g_shape_mu;
+int64_t g_n_wide = 512, g_n_mid = 128;
+inline int shape_for(int n) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    return n >= g_n_wide ? 0 : (n >= g_n_mid ? 1 : 2);
+}
 constexpr int kKP0 = 4, kKP1 = 8;  // k-panel rows of the two sparse-k shapes
 
 // Largest t with start[t] <= v (start ascending, start[0] == 0).
@@ -653,6 +660,14 @@ afmm_status afmm_batched_plan_destroy(afmm_plan* pl) {
     if (pl->cap) (void)hipStreamDestroy(pl->cap);
     if (pl->mem) (void)hipFree(pl->mem);
     delete pl;
+    return AFMM_OK;
+}
+
+afmm_status afmm_set_batch_shapes(int64_t n_wide, int64_t n_mid) {
+    if (n_mid < 1 || n_wide < n_mid) return AFMM_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_n_wide = n_wide;
+    g_n_mid = n_mid;
     return AFMM_OK;
 }
 

@@ -1,5 +1,7 @@
 """Autotuner for the strict path: times every compiled kernel configuration on
-representative inputs and writes the fastest per (case, size) to a tuning table.
+representative inputs and writes the fastest per (case, size) to a tuning table,
+and the batched kernel's tile-shape thresholds measured on the 512-product
+workload.
 
     python -m paper_1308_2400_amd.tune [--out tune_cache.json] [--quick]
 
@@ -114,11 +116,78 @@ def to_table(results):
     return entries
 
 
+# Size thresholds (n_wide, n_mid) of the batched kernel's tile shapes tried by
+# the batch sweep; (512, 128) is the built-in pair.
+BATCH_GRID = [(w, m) for w in (384, 512, 640, 704, 768, 832, 896, 1025)
+              for m in (64, 96, 128, 192) if m <= w]
+
+
+def pick_batch_shapes(timings, default=(512, 128)):
+    """timings: [(ms, (n_wide, n_mid))]; the fastest pair, the built-in one on ties."""
+    best_ms = min(ms for ms, _ in timings)
+    tied = [pair for ms, pair in timings if ms == best_ms]
+    pair = tuple(default) if tuple(default) in tied else tied[0]
+    return {"n_wide": pair[0], "n_mid": pair[1], "ms": best_ms,
+            "all": [[list(pr), ms] for ms, pr in sorted(timings)]}
+
+
+def tune_batch(reps=5, log=print):
+    """Times one plan launch of the 512-product workload for every threshold pair;
+    every pair's products must equal the built-in pair's bit for bit."""
+    import torch
+    import paper_1308_2400_amd as afmm
+    sys.path.insert(0, ROOT)
+    import gen
+    probs = []
+    for w in gen.batched_512():
+        X = torch.from_numpy(w.X()).cuda()
+        Y = torch.from_numpy(w.Y()).cuda()
+        Z = torch.empty((w.n, w.n), dtype=torch.float32, device="cuda")
+        probs.append((w.case, X, Y, Z))
+    ref, timings = None, []
+    try:
+        for pair in [(512, 128)] + [p for p in BATCH_GRID if p != (512, 128)]:
+            afmm.set_batch_shapes(*pair)
+            plan = afmm.Plan(probs)
+            plan.launch()
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = [Z.clone() for *_, Z in probs]
+            elif not all(torch.equal(a.view(torch.int32), Z.view(torch.int32))
+                         for a, (*_, Z) in zip(ref, probs)):
+                raise RuntimeError(f"batch shapes {pair} change the products")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                plan.launch()
+            e1.record()
+            e1.synchronize()
+            plan.close()
+            ms = e0.elapsed_time(e1) / reps
+            timings.append((ms, pair))
+            log(f"tune batch shapes n_wide={pair[0]} n_mid={pair[1]}: {ms:.3f} ms")
+    finally:
+        afmm.set_batch_shapes()
+    r = pick_batch_shapes(timings)
+    log(f"tune batch shapes: best ({r['n_wide']}, {r['n_mid']}) {r['ms']:.3f} ms")
+    return r
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--out", default=os.path.join(_HERE, "tune_cache.json"))
     p.add_argument("--quick", action="store_true")
+    p.add_argument("--batch-only", action="store_true",
+                   help="re-tune only the batched shapes, keeping the table's other entries")
     a = p.parse_args()
+    if a.batch_only:
+        with open(a.out) as f:
+            out = json.load(f)
+        out["batch_shapes"] = tune_batch(log=lambda m: print(m, flush=True))
+        with open(a.out, "w") as f:
+            json.dump(out, f, indent=1)
+        print(f"wrote {a.out}", flush=True)
+        return
     if a.quick:
         sizes = [("B", 1024), ("B", 4096), ("A", 1024), ("A", 4096)]
     else:
@@ -126,8 +195,9 @@ def main():
                  ("A", 256), ("A", 1024), ("A", 2048), ("A", 4096), ("A", 8192)]
     t = time.time()
     results = tune(sizes, log=lambda m: print(m, flush=True))
+    batch = tune_batch(log=lambda m: print(m, flush=True))
     out = {"generated_by": "python -m paper_1308_2400_amd.tune", "seconds": time.time() - t,
-           "entries": to_table(results), "results": results}
+           "entries": to_table(results), "results": results, "batch_shapes": batch}
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
     print(f"wrote {a.out}", flush=True)

@@ -213,3 +213,30 @@ def test_batched_512_sampled(dev):
         Z = Zd.cpu().numpy()[rows]
         assert np.array_equal(Z.view(np.uint32), Zref.view(np.uint32)), (t, case, n)
     plan.close()
+
+
+def test_batched_shape_thresholds_same_bits(dev):
+    """Plans built under other tile-shape thresholds (every problem on the widest
+    tiles, or every one on the narrowest) give the built-in plan's bits; bad
+    thresholds are refused."""
+    import torch
+    import paper_1308_2400_amd as afmm
+    probs = _mixed_problems(20, 9, n_max=700)
+    plan, dprobs = _run_plan(dev, probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = [Zd.clone() for *_, Zd in dprobs]
+    plan.close()
+    try:
+        for pair in ((1, 1), (1 << 20, 1 << 20), (300, 64)):
+            afmm.set_batch_shapes(*pair)
+            plan, dprobs2 = _run_plan(dev, probs)
+            plan.launch()
+            torch.cuda.synchronize()
+            for t, (a, (*_, Zd)) in enumerate(zip(ref, dprobs2)):
+                assert torch.equal(a.view(torch.int32), Zd.view(torch.int32)), (pair, t)
+            plan.close()
+        assert afmm.afmm_set_batch_shapes(64, 128) == 1
+        assert afmm.afmm_set_batch_shapes(64, 0) == 1
+    finally:
+        afmm.set_batch_shapes()

@@ -35,3 +35,18 @@ def test_table_ranges_meet_at_geometric_midpoints():
 def test_candidates_cover_every_compiled_mapping():
     assert {c[0] for c in tune.CANDIDATES} == {0, 2, 3, 4}
     assert set(tune.TABLE_MAPPINGS) == {0, 2, 3}
+
+
+def test_batch_shape_pick():
+    t = [(26.9, (512, 128)), (26.1, (384, 96)), (27.5, (256, 64))]
+    r = tune.pick_batch_shapes(t)
+    assert (r["n_wide"], r["n_mid"]) == (384, 96) and r["ms"] == 26.1
+    assert [p for p, _ in r["all"]][0] == [384, 96]
+    # a tie keeps the built-in pair
+    r = tune.pick_batch_shapes([(26.0, (384, 96)), (26.0, (512, 128))])
+    assert (r["n_wide"], r["n_mid"]) == (512, 128)
+
+
+def test_batch_grid_is_ordered_and_holds_the_builtin_pair():
+    assert (512, 128) in tune.BATCH_GRID
+    assert all(1 <= m <= w for w, m in tune.BATCH_GRID)
