@@ -112,7 +112,7 @@ def test_config_table(afmm):
     assert afmm.config_supported("B", (0, 8, 8, 8))
     assert afmm.config_supported("A", (0, 4, 4, 4))
     assert not afmm.config_supported("B", (0, 3, 3, 3))
-    assert not afmm.config_supported("B", (1, 8, 8, 8))  # base-uniform is case A only
+    assert not afmm.config_supported("B", (1, 8, 8, 8))  # mapping 1 is not compiled
     for n in (1, 100, 256, 2048, 4096, 16384):
         assert afmm.config_supported("B", afmm.default_config("B", n))
     assert afmm.config_supported("B", (0, 8, 8, 8, 2))
@@ -184,3 +184,31 @@ def test_workspace_of_the_list_forms(afmm):
         assert lists <= ws <= lists + 4 * n * 2 + 4 * 256
     # unsupported shapes of the form are not compiled
     assert afmm.workspace_size("B", n, config=(7, 1, 24, 16, 1, 16)) == 0
+
+
+def test_plain_strict_workspace_covers_every_form(afmm):
+    """From n = 1024 to 16384 the plain strict call may take the compacted-base or
+    the row-list form, so its workspace covers their lists too; outside that
+    range it is the size-keyed form's alone."""
+    for case in ("A", "B"):
+        c = afmm._case_id(case)
+        for n in (1023, 1024, 4096, 16384, 16385):
+            plain = afmm.afmm_workspace_size(c, n, 0)
+            keyed = afmm.workspace_size(case, n, config=afmm.default_config(case, n))
+            if 1024 <= n <= 16384:
+                assert plain >= keyed + 16 * n * n  # row lists of both factors: 8 B each
+                assert plain >= afmm.workspace_size(case, n, config=(4, 2, 16, 8, 1, 16))
+            else:
+                assert plain == keyed
+
+
+def test_new_entry_points_reject_bad_arguments_on_host(afmm):
+    assert afmm.afmm_set_batch_shapes(64, 128) == 1   # n_mid above n_wide
+    assert afmm.afmm_set_batch_shapes(64, 0) == 1
+    assert afmm.afmm_set_batch_shapes(512, 128) == 0  # the built-in pair
+    afmm.load_tuning()  # back to the tuned pair
+    out = 1 << 20
+    assert afmm.afmm_plain_form(0, 0, 4096, 8192, out, None, 0, None) == 1
+    assert afmm.afmm_plain_form(2, 64, 4096, 8192, out, None, 0, None) == 1
+    assert afmm.afmm_plain_form(1, 64, None, 8192, out, None, 0, None) == 1
+    assert afmm.afmm_plain_form(1, 64, 4096, 8192, None, None, 0, None) == 1
