@@ -46,15 +46,38 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as
 // plane is written in 16-byte pieces, eight lanes to a 128-byte row segment.
 // TRANS: output row o, column k come from in[k][o]; else from in[o][k].
 // Outputs are [rows_pad x ld] with zeros outside rows x cols.
+// vec: every input row starts 16-byte aligned.  Turned round, a lane reads four
+// consecutive output rows of one input row with one 16-byte load (16 lanes to a
+// 256-byte row segment) and scatters them down a tile column.
 template <bool TRANS, typename T>
 __device__ __forceinline__ void load_block(const T* __restrict__ in, int rows, int cols, int64_t ldi,
-                                           int o0, int c0, T (*tile)[65]) {
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    for (int t = ly; t < 64; t += 4) {
-        const int r = TRANS ? c0 + t : o0 + t;  // input row
-        const int c = TRANS ? o0 + lx : c0 + lx;
-        const T v = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : T(0);
-        if (TRANS) tile[lx][t] = v; else tile[t][lx] = v;
+                                           bool vec, int o0, int c0, T (*tile)[65]) {
+    if (TRANS) {
+        const int j4 = (threadIdx.x & 15) * 4, tt = threadIdx.x >> 4;
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int t = tt + 16 * it, r = c0 + t, c = o0 + j4;  // input row r, columns c..c+3
+            const T* src = in + (int64_t)r * ldi + c;
+            T v[4];
+            if (r < rows && vec && c + 4 <= cols) {
+                const uint4 w = *reinterpret_cast<const uint4*>(src);
+                v[0] = __builtin_bit_cast(T, w.x);
+                v[1] = __builtin_bit_cast(T, w.y);
+                v[2] = __builtin_bit_cast(T, w.z);
+                v[3] = __builtin_bit_cast(T, w.w);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (r < rows && c + q < cols) ? src[q] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tile[j4 + q][t] = v[q];
+        }
+    } else {
+        const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+        for (int t = ly; t < 64; t += 4) {
+            const int r = o0 + t, c = c0 + lx;
+            tile[t][lx] = (r < rows && c < cols) ? in[(int64_t)r * ldi + c] : T(0);
+        }
     }
 }
 
@@ -63,8 +86,8 @@ __device__ __forceinline__ void split_real_block(const float* __restrict__ in, i
                                                  int64_t ldi, uint16_t* __restrict__ hi,
                                                  uint16_t* __restrict__ mid,
                                                  uint16_t* __restrict__ lo, int64_t ld, int o0,
-                                                 int c0, float (*tile)[65]) {
-    load_block<TRANS>(in, rows, cols, ldi, o0, c0, tile);
+                                                 int c0, bool vec, float (*tile)[65]) {
+    load_block<TRANS>(in, rows, cols, ldi, vec, o0, c0, tile);
     __syncthreads();
     for (int h = 0; h < 2; ++h) {
         const int c = threadIdx.x + 256 * h, o = c >> 3, kq = (c & 7) * 8;
@@ -91,8 +114,8 @@ __device__ __forceinline__ void split_real_block(const float* __restrict__ in, i
 template <bool TRANS>
 __device__ __forceinline__ void int_bf16_block(const int32_t* __restrict__ in, int rows, int cols,
                                                int64_t ldi, uint16_t* __restrict__ out, int64_t ld,
-                                               int o0, int c0, int32_t (*tile)[65]) {
-    load_block<TRANS>(in, rows, cols, ldi, o0, c0, tile);
+                                               int o0, int c0, bool vec, int32_t (*tile)[65]) {
+    load_block<TRANS>(in, rows, cols, ldi, vec, o0, c0, tile);
     __syncthreads();
     for (int h = 0; h < 2; ++h) {
         const int c = threadIdx.x + 256 * h, o = c >> 3, kq = (c & 7) * 8;
@@ -102,6 +125,75 @@ __device__ __forceinline__ void int_bf16_block(const int32_t* __restrict__ in, i
             const int32_t v = tile[o][kq + e];
             // a count <= 0 adds nothing; 1..256 are exact in bfloat16
             const uint32_t b = v <= 0 ? 0u : bf16_bits_rne((float)v);
+            const int w = e >> 1;
+            p[w] = (e & 1) ? p[w] | (b << 16) : b;
+        }
+        *reinterpret_cast<uint4*>(out + (int64_t)(o0 + o) * ld + c0 + kq) =
+            make_uint4(p[0], p[1], p[2], p[3]);
+    }
+}
+
+// The same conversions for a factor that is not turned round (output row o,
+// column k from in[o][k]): no LDS, each lane reads the eight k it writes, with
+// two 16-byte loads where the row allows them (vec: every row starts 16-byte
+// aligned).
+__device__ __forceinline__ void load8(const uint32_t* __restrict__ in, int rows, int cols,
+                                      int64_t ldi, bool vec, int o, int k, uint32_t (&v)[8]) {
+    const uint32_t* src = in + (int64_t)o * ldi + k;
+    if (o < rows && vec && k + 8 <= cols) {
+        const uint4 a = reinterpret_cast<const uint4*>(src)[0];
+        const uint4 b = reinterpret_cast<const uint4*>(src)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (o < rows && k + e < cols) ? src[e] : 0u;
+    }
+}
+
+__device__ __forceinline__ void split_real_direct(const float* __restrict__ in, int rows,
+                                                  int cols, int64_t ldi, bool vec,
+                                                  uint16_t* __restrict__ hi,
+                                                  uint16_t* __restrict__ mid,
+                                                  uint16_t* __restrict__ lo, int64_t ld, int o0,
+                                                  int c0) {
+    for (int h = 0; h < 2; ++h) {
+        const int c = threadIdx.x + 256 * h, o = c >> 3, kq = (c & 7) * 8;
+        uint32_t v[8];
+        load8(reinterpret_cast<const uint32_t*>(in), rows, cols, ldi, vec, o0 + o, c0 + kq, v);
+        uint32_t ph[4], pm[4], pl[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float x = __uint_as_float(v[e]);
+            const uint32_t bh = bf16_bits_rne(x);
+            const float r1 = x - bf16_bits_to_f32(bh);
+            const uint32_t bm = bf16_bits_rne(r1);
+            const uint32_t bl = bf16_bits_rne(r1 - bf16_bits_to_f32(bm));
+            const int w = e >> 1, sh = (e & 1) * 16;
+            ph[w] = (e & 1) ? ph[w] | (bh << sh) : bh;
+            pm[w] = (e & 1) ? pm[w] | (bm << sh) : bm;
+            pl[w] = (e & 1) ? pl[w] | (bl << sh) : bl;
+        }
+        const int64_t off = (int64_t)(o0 + o) * ld + c0 + kq;
+        *reinterpret_cast<uint4*>(hi + off) = make_uint4(ph[0], ph[1], ph[2], ph[3]);
+        *reinterpret_cast<uint4*>(mid + off) = make_uint4(pm[0], pm[1], pm[2], pm[3]);
+        *reinterpret_cast<uint4*>(lo + off) = make_uint4(pl[0], pl[1], pl[2], pl[3]);
+    }
+}
+
+__device__ __forceinline__ void int_bf16_direct(const int32_t* __restrict__ in, int rows, int cols,
+                                                int64_t ldi, bool vec, uint16_t* __restrict__ out,
+                                                int64_t ld, int o0, int c0) {
+    for (int h = 0; h < 2; ++h) {
+        const int c = threadIdx.x + 256 * h, o = c >> 3, kq = (c & 7) * 8;
+        uint32_t v[8];
+        load8(reinterpret_cast<const uint32_t*>(in), rows, cols, ldi, vec, o0 + o, c0 + kq, v);
+        uint32_t p[4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int32_t x = (int32_t)v[e];
+            // a count <= 0 adds nothing; 1..256 are exact in bfloat16
+            const uint32_t b = x <= 0 ? 0u : bf16_bits_rne((float)x);
             const int w = e >> 1;
             p[w] = (e & 1) ? p[w] | (b << 16) : b;
         }
@@ -121,13 +213,21 @@ __global__ __launch_bounds__(256) void split_prep_kernel(SplitPrepArgs a) {
     const int k_tiles = (int)(a.ld / 64);
     int b = blockIdx.x;
     if (b < a.int_blocks) {
-        int_bf16_block<CASE_A>(a.I, a.i_rows, a.i_cols, a.ldi, a.ip, a.ld, (b / k_tiles) * 64,
-                               (b % k_tiles) * 64, reinterpret_cast<int32_t(*)[65]>(tile));
+        const int o0 = (b / k_tiles) * 64, c0 = (b % k_tiles) * 64;
+        if (CASE_A)
+            int_bf16_block<true>(a.I, a.i_rows, a.i_cols, a.ldi, a.ip, a.ld, o0, c0, a.i_vec,
+                                 reinterpret_cast<int32_t(*)[65]>(tile));
+        else
+            int_bf16_direct(a.I, a.i_rows, a.i_cols, a.ldi, a.i_vec, a.ip, a.ld, o0, c0);
     } else {
         b -= a.int_blocks;
-        split_real_block<!CASE_A>(a.R, a.r_rows, a.r_cols, a.ldr, a.hi, a.mid, a.lo, a.ld,
-                                  (b / k_tiles) * 64, (b % k_tiles) * 64,
-                                  reinterpret_cast<float(*)[65]>(tile));
+        const int o0 = (b / k_tiles) * 64, c0 = (b % k_tiles) * 64;
+        if (CASE_A)
+            split_real_direct(a.R, a.r_rows, a.r_cols, a.ldr, a.r_vec, a.hi, a.mid, a.lo, a.ld,
+                              o0, c0);
+        else
+            split_real_block<true>(a.R, a.r_rows, a.r_cols, a.ldr, a.hi, a.mid, a.lo, a.ld, o0,
+                                   c0, a.r_vec, reinterpret_cast<float(*)[65]>(tile));
     }
 }
 
@@ -454,6 +554,8 @@ hipError_t launch_split_prepare(bool case_a, int m, int k, int n, const void* X,
     a.r_tiles_o = L.rows_real / 64;
     a.ld = L.ld;
     a.int_blocks = (int)((int64_t)a.i_tiles_o * (L.ld / 64));
+    a.i_vec = a.ldi % 4 == 0 && reinterpret_cast<uintptr_t>(a.I) % 16 == 0;
+    a.r_vec = a.ldr % 4 == 0 && reinterpret_cast<uintptr_t>(a.R) % 16 == 0;
     return launch_split_prep(case_a, a, s);
 }
 

@@ -22,6 +22,8 @@ struct SplitPrepArgs {
     int r_tiles_o;
     int64_t ld;
     int int_blocks;
+    // every row of I (of R) starts 16-byte aligned: 16-byte loads allowed
+    bool i_vec = false, r_vec = false;
 };
 hipError_t launch_split_prep(bool case_a, const SplitPrepArgs& a, hipStream_t s);
 // Z (M x N, pitch ldz) from the integer plane I and the term planes S0..S2
