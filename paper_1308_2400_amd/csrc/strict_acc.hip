@@ -37,26 +37,38 @@ AccLists acc_lists_at(uint8_t* p, int n_c, int n_k, int C) {
 }
 
 // One wave per segment (band, k).  Lane l owns the band's columns l + 64 m
-// (m < C), all of one residue modulo 64; an element (row, column) of the Z
-// tile sits in LDS bank (row offset + column) mod 64 (and mod 32), so lanes
-// that take columns of distinct residues read and write a row without bank
-// conflicts.  With total non-zero bases in the band, the segment gets
-// nch = ceil(total / 64) chunks of 64 slots: slot (q, l) holds lane l's q-th
-// non-zero column when it has one (its own residue), lanes with more than nch
-// non-zero columns hand the rest to the free slots of other lanes (these share
-// a bank with their owner), and slots left over get the lane's sink column
-// CT + l with a +0.0 base.  The chunks are padded to a multiple of E (the
-// entries a lane takes per k).  An entry is {bits of the base, byte offset of
-// its column in an LDS row}; the segment's length is the padded slot count, 0
-// when the band has no non-zero base at this k.  Which slot adds a base
-// changes nothing in the sums: each column appears once per k.
+// (m < C), all of one residue modulo 64.  LDS serves a wave-wide 32-bit access
+// as two half-waves (lanes 0-31, then 32-63), each over 32 banks of 4 bytes, and
+// an element (row, column) of the Z tile sits in bank (row offset + column) mod
+// 32: lanes l and l ^ 32 share a bank but are served in different half-waves,
+// and every column a lane owns, its sink column CT + l included, is in that
+// lane's bank.  With total non-zero bases in the band the segment gets
+// nch = ceil(total / 64) chunks of 64 slots; slot (q, l) holds lane l's q-th
+// non-zero column when it has one.  A lane with more than nch hands the rest
+// on: first to the free slots of lane l ^ 32 (same bank, other half-wave, so
+// still no conflict), then, once both lanes of its bank are full, to free
+// slots of other lanes, alternating between the half-waves so that a bank
+// takes one extra access per half-wave before it takes a second (each extra
+// access costs its half-wave one conflict cycle).  Slots left over get the
+// lane's sink column with a +0.0 base.  The chunks are padded to a multiple of
+// E (the entries a lane takes per k).  An entry is {bits of the base, byte
+// offset of its column in an LDS row}; the segment's length is the padded slot
+// count, 0 when the band has no non-zero base at this k.  Which slot adds a
+// base changes nothing in the sums: each column appears once per k.
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __global__ __launch_bounds__(256) void compact_base_kernel(const float* __restrict__ Q,
                                                            int64_t ldq, int n_k, int n_c, int C,
                                                            int E, int64_t n_k_pad, int64_t n_segs,
                                                            uint2* __restrict__ ent,
                                                            int32_t* __restrict__ lens,
                                                            const uint32_t* __restrict__ gate) {
-    // per wave: the columns handed on, in hand-over order (CT <= 4096 of them)
+    // per wave: the columns handed to lanes other than lane ^ 32, those bound
+    // for the upper half-wave first (CT <= 4096 of them)
     __shared__ uint16_t handed[4][kWave * 64];
     AFMM_GATE(gate);
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
@@ -95,35 +107,84 @@ __global__ __launch_bounds__(256) void compact_base_kernel(const float* __restri
         const int c = lane + kWave * m;
         out[s * kWave + lane] = make_uint2(__float_as_uint(q[c]), (uint32_t)c * 4u);
     }
-    // columns beyond nch go to the free slots of lanes with fewer than nch
-    const int ov = a - own, holes = nch - own;
-    int ov_x = ov, h_x = holes;  // inclusive scans over the lanes
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int t1 = __shfl_up(ov_x, off), t2 = __shfl_up(h_x, off);
-        if (lane >= off) {
-            ov_x += t1;
-            h_x += t2;
+    // the partner's columns beyond its nch into this lane's free slots, and
+    // this lane's beyond nch into the partner's
+    const int partner = lane ^ (kWave / 2);
+    const uint64_t mine_p = shfl_u64(mine, partner);
+    const int a_p = __popcll(mine_p), own_p = a_p < nch ? a_p : nch;
+    const int give = min(a - own, nch - own_p), recv = min(a_p - own_p, nch - own);
+    {
+        uint64_t rp = mine_p;
+        for (int s = 0; s < own_p; ++s) rp &= rp - 1;
+        for (int s = 0; s < recv; ++s) {
+            const int m = __ffsll((unsigned long long)rp) - 1;
+            rp &= rp - 1;
+            const int c = partner + kWave * m;
+            out[(own + s) * kWave + lane] = make_uint2(__float_as_uint(q[c]), (uint32_t)c * 4u);
         }
     }
-    const int ov_total = __shfl(ov_x, kWave - 1);
-    ov_x -= ov;
-    h_x -= holes;
-    if (ov_total > 0) {
-        for (int u = 0; u < ov; ++u) {
+    for (int u = 0; u < give; ++u) rest &= rest - 1;
+    const int ov = a - own - give, holes = nch - own - recv;  // left after the pairing
+    // the lane's j-th remaining column goes to the other half-wave for even j,
+    // to its own for odd j
+    const bool up = lane >= kWave / 2;
+    const int n_up = up ? ov / 2 : (ov + 1) / 2, n_lo = ov - n_up;
+    // exclusive scans over the lanes: entries bound up / down, free slots above / below
+    int up_x = n_up, lo_x = n_lo, hu_x = up ? holes : 0, hl_x = up ? 0 : holes;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t1 = __shfl_up(up_x, off), t2 = __shfl_up(lo_x, off);
+        const int t3 = __shfl_up(hu_x, off), t4 = __shfl_up(hl_x, off);
+        if (lane >= off) {
+            up_x += t1;
+            lo_x += t2;
+            hu_x += t3;
+            hl_x += t4;
+        }
+    }
+    const int ue = __shfl(up_x, kWave - 1), le = __shfl(lo_x, kWave - 1);
+    const int uh = __shfl(hu_x, kWave - 1), lh = __shfl(hl_x, kWave - 1);
+    up_x -= n_up;
+    lo_x -= n_lo;
+    if (ue + le > 0) {
+        // list: entries bound up at [0, ue), entries bound down at [ue, ue + le)
+        int iu = 0, il = 0;
+        for (int j = 0; j < ov; ++j) {
             const int m = __ffsll((unsigned long long)rest) - 1;
             rest &= rest - 1;
-            handed[wv][ov_x + u] = (uint16_t)(lane + kWave * m);
+            const uint16_t c = (uint16_t)(lane + kWave * m);
+            if ((j & 1) == (up ? 1 : 0))
+                handed[wv][up_x + iu++] = c;
+            else
+                handed[wv][ue + lo_x + il++] = c;
         }
         // the wave's own LDS writes, read back by other lanes of the wave
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    for (int s = own; s < nch; ++s) {
-        const int t = h_x + (s - own);
+    // free slots take the entries bound for their half-wave; a half-wave with
+    // more entries than free slots passes the excess to the other one (the
+    // slots suffice: 64 nch >= total)
+    const int rank0 = up ? hu_x - holes : hl_x - holes;
+    for (int s = own + recv; s < nch; ++s) {
+        const int t = rank0 + (s - own - recv);
+        int idx = -1;
+        if (up) {
+            const int fill = min(ue, uh);
+            if (t < fill)
+                idx = t;
+            else if (le > lh && t - fill < le - lh)
+                idx = ue + lh + (t - fill);
+        } else {
+            const int fill = min(le, lh);
+            if (t < fill)
+                idx = ue + t;
+            else if (ue > uh && t - fill < ue - uh)
+                idx = uh + (t - fill);
+        }
         uint2 e = sink;
-        if (t < ov_total) {
-            const int c = handed[wv][t];
+        if (idx >= 0) {
+            const int c = handed[wv][idx];
             e = make_uint2(__float_as_uint(q[c]), (uint32_t)c * 4u);
         }
         out[s * kWave + lane] = e;

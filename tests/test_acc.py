@@ -82,12 +82,17 @@ def test_acc_sizes_and_densities(dev, case, n):
 
 
 @pytest.mark.parametrize("case", ["A", "B"])
-@pytest.mark.parametrize("pattern", ["one_residue", "two_residues", "clustered"])
+@pytest.mark.parametrize("pattern", ["one_residue", "two_residues", "clustered", "bank_pair",
+                                     "lower_full", "upper_full"])
 def test_acc_uneven_bank_classes(dev, case, pattern):
     """Non-zero bases piled into few residues modulo 64 of the lane axis (i in
-    case A, j in case B): the slots of a k take each lane's own columns first
-    and hand the rest to other lanes' free slots; every base must still be
-    added exactly once per k."""
+    case A, j in case B): the slots of a k take each lane's own columns first,
+    hand the rest to the free slots of the lane 32 away (same LDS bank, other
+    half-wave), then to other lanes' free slots alternating between the
+    half-waves, passing the excess of a full half-wave to the other one; every
+    base must still be added exactly once per k.  bank_pair fills both lanes of
+    one bank; lower_full and upper_full leave one half-wave no free slot while
+    entries are bound for it."""
     n = 700
     X, Y = _inputs(case, n, 404 + len(pattern), 1.0)
     real = X if case == "A" else Y
@@ -96,6 +101,12 @@ def test_acc_uneven_bank_classes(dev, case, pattern):
         keep = idx % 64 == 5
     elif pattern == "two_residues":
         keep = (idx % 64 == 5) | (idx % 64 == 40)
+    elif pattern == "bank_pair":
+        keep = (idx % 64 == 5) | (idx % 64 == 37)
+    elif pattern == "lower_full":
+        keep = idx % 64 < 48  # lanes 0-47 overflow, lanes 48-63 have free slots
+    elif pattern == "upper_full":
+        keep = idx % 64 >= 16  # lanes 16-63 overflow, lanes 0-15 have free slots
     else:
         keep = (idx >= 100) & (idx < 100 + 150)  # one run: every residue, two or three each
     if case == "A":
