@@ -180,6 +180,29 @@ afmm_status afmm_split_terms(afmm_case c, int64_t n, const void *X, const void *
                              size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * The compacted-base form's lists of non-zero bases, read back (for checking
+ * the list builder; not needed for computing products).  Q: a k x n_c
+ * row-major binary32 matrix in device memory, leading dimension ldq >= n_c,
+ * row t holding the bases of one k (case B: Y; case A: X transposed).  With
+ * CT = 64*C columns per band (C in 1..64), bands = ceil(n_c / CT),
+ * k_pad = round_up(k, 16) and E = max(1, C/16), writes in device memory:
+ *   d_entries: [bands][k_pad][CT] pairs of uint32 {bits of Q[t][b*CT + c],
+ *              4*c} (the byte offset of column c in a row of the band); slot
+ *              q*64 + l of a segment is the q-th entry lane l adds.  Lane l
+ *              owns the columns c = l (mod 64) and takes them first; a lane's
+ *              surplus goes to lane l ^ 32 first, then alternately to free
+ *              slots of the other and of its own half-wave; free slots hold
+ *              {+0.0, 4*(CT + l)} (the lane's sink column);
+ *   d_lens:    [bands][k_pad] int32, the slots in use: ceil(nnz / 64) rounded
+ *              up to a multiple of E, times 64; 0 when the segment has no
+ *              non-zero base (-0.0 counts as zero, NaN as non-zero).  Slots
+ *              past the length are not written.
+ * Asynchronous on `stream`.
+ */
+afmm_status afmm_base_lists(const float *Q, int64_t k, int64_t n_c, int64_t ldq, int32_t C,
+                            uint32_t *d_entries, int32_t *d_lens, hipStream_t stream);
+
+/*
  * Synchronous data check: runs the counting pass on `stream`, waits for it,
  * and returns AFMM_ERR_NEGATIVE_INT, AFMM_ERR_INT_RANGE (split mode, an
  * entry > 256), AFMM_ERR_COUNT_OVERFLOW or AFMM_OK.

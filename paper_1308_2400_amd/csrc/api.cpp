@@ -602,6 +602,21 @@ afmm_status afmm_split_terms(afmm_case c, int64_t n, const void* X, const void* 
     return AFMM_OK;
 }
 
+afmm_status afmm_base_lists(const float* Q, int64_t k, int64_t n_c, int64_t ldq, int32_t C,
+                            uint32_t* d_entries, int32_t* d_lens, hipStream_t stream) {
+    if (!Q || !d_entries || !d_lens || k < 1 || k > AFMM_MAX_N || n_c < 1 || n_c > AFMM_MAX_N ||
+        ldq < n_c || ldq > kMaxLd || C < 1 || C > 64)
+        return AFMM_ERR_INVALID_ARG;
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    AccLists L;
+    L.ent = reinterpret_cast<uint2*>(d_entries);
+    L.lens = d_lens;
+    L.n_k_pad = round_up(k, kAccKPad);
+    AFMM_HIP(launch_compact_base(Q, ldq, (int)k, (int)n_c, C, L, stream));
+    return AFMM_OK;
+}
+
 afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, afmm_mode mode,
                           hipStream_t stream) {
     if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;

@@ -17,7 +17,7 @@
 
 namespace afmm {
 
-constexpr int kAccKP = 16;  // k padding of the segment table (covers panels of 8 and 16 k)
+constexpr int kAccKP = kAccKPad;
 constexpr int kAccWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), other counters at their maxima
 
 size_t acc_lists_bytes(int n_c, int n_k, int C) {

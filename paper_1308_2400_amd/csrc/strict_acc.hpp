@@ -8,6 +8,7 @@ namespace afmm {
 // Band of CT = 64 * C lane columns.  The compacted base of band b holds, per k
 // in [0, n_k_pad), a segment of CT entries {bits of Q[k][c], c - b*CT} for the
 // columns c of the band with a non-zero base, in ascending c, and its length.
+constexpr int kAccKPad = 16;  // k padding of the segment table (covers panels of 8 and 16 k)
 struct AccLists {
     uint2* ent;       // [n_bands][n_k_pad][CT]
     int32_t* lens;    // [n_bands][n_k_pad]
