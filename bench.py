@@ -500,8 +500,14 @@ def low_density(args):
             Xd, Yd = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
             adds = afmm.count_adds(case, Xd, Yd)
             steps = max(args.steps, 3)
-            Zd = afmm.multiply(case, Xd, Yd)
-            ms_default = event_time_ms(lambda: afmm.multiply(case, Xd, Yd, out=Zd), steps, stream)
+            # the plain call (it chooses its form on the device), the size-keyed
+            # form and the row-list form, each called explicitly
+            Zp = afmm.multiply(case, Xd, Yd)
+            ms_plain = event_time_ms(lambda: afmm.multiply(case, Xd, Yd, out=Zp), steps, stream)
+            keyed = afmm.default_config(case, n)
+            Zd = afmm.multiply(case, Xd, Yd, config=keyed)
+            ms_default = event_time_ms(lambda: afmm.multiply(case, Xd, Yd, out=Zd, config=keyed),
+                                       steps, stream)
             Zl = afmm.multiply(case, Xd, Yd, config=LOW_DENSITY_CONFIG)
             ms_low = event_time_ms(
                 lambda: afmm.multiply(case, Xd, Yd, out=Zl, config=LOW_DENSITY_CONFIG), steps,
@@ -509,22 +515,25 @@ def low_density(args):
             sample = [n // 3, n - 1]
             Zr, _ = oracle.strict_f32(case, X[sample], Y, rows=sample, x_rows_only=True)
             ok = bool(np.array_equal(Zl.cpu().numpy()[sample].view(np.uint32), Zr.view(np.uint32))
-                      and torch.equal(Zl.view(torch.int32), Zd.view(torch.int32)))
+                      and torch.equal(Zl.view(torch.int32), Zd.view(torch.int32))
+                      and torch.equal(Zp.view(torch.int32), Zd.view(torch.int32)))
+            form = afmm.plain_form(case, Xd, Yd)
             rows.append({"case": case, "n": n, "d1": d, "d2": d, "adds": adds,
-                         "default_ms": ms_default,
-                         "default_config": list(afmm.default_config(case, n)),
+                         "plain_ms": ms_plain, "plain_form": form,
+                         "default_ms": ms_default, "default_config": list(keyed),
                          "low_density_ms": ms_low, "speedup": ms_default / ms_low,
                          "bitexact_sampled_rows": ok})
-            log(f"lowdensity {case} n={n}: {adds:.3e} adds, default {ms_default:.3f} ms, "
+            log(f"lowdensity {case} n={n}: {adds:.3e} adds, plain call {ms_plain:.3f} ms "
+                f"(mapping {form}), size-keyed form {ms_default:.3f} ms, "
                 f"low-density form {ms_low:.3f} ms")
-            del Xd, Yd, Zd, Zl
+            del Xd, Yd, Zd, Zl, Zp
             torch.cuda.empty_cache()
 
     def exponent(case, key):
         sel = [r for r in rows if r["case"] == case]
         return float(np.polyfit(np.log([r["n"] for r in sel]), np.log([r[key] for r in sel]),
                                 1)[0])
-    fits = {case: {k: exponent(case, k) for k in ("adds", "default_ms", "low_density_ms")}
+    fits = {case: {k: exponent(case, k) for k in ("adds", "plain_ms", "default_ms", "low_density_ms")}
             for case in ("A", "B")}
     out = {"metric": "low-density regime d1*d2 = 1/n: strict AFMM time per product", "unit": "ms",
            "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded generator)",
