@@ -212,3 +212,14 @@ def test_new_entry_points_reject_bad_arguments_on_host(afmm):
     assert afmm.afmm_plain_form(2, 64, 4096, 8192, out, None, 0, None) == 1
     assert afmm.afmm_plain_form(1, 64, None, 8192, out, None, 0, None) == 1
     assert afmm.afmm_plain_form(1, 64, 4096, 8192, None, None, 0, None) == 1
+    # the compacted-base list read-back: k, n_c, ldq and C checked before any device work
+    q, ent, lens = 4096, 8192, 1 << 16
+    assert afmm.afmm_base_lists(q, 0, 64, 64, 1, ent, lens, None) == 1      # k < 1
+    assert afmm.afmm_base_lists(q, 4, 0, 64, 1, ent, lens, None) == 1      # n_c < 1
+    assert afmm.afmm_base_lists(q, 4, 64, 63, 1, ent, lens, None) == 1     # ldq < n_c
+    assert afmm.afmm_base_lists(q, 4, 64, 64, 0, ent, lens, None) == 1     # C < 1
+    assert afmm.afmm_base_lists(q, 4, 64, 64, 65, ent, lens, None) == 1    # C > 64
+    assert afmm.afmm_base_lists(None, 4, 64, 64, 1, ent, lens, None) == 1  # null pointers
+    assert afmm.afmm_base_lists(q, 4, 64, 64, 1, None, lens, None) == 1
+    assert afmm.afmm_base_lists(q, 4, 64, 64, 1, ent, None, None) == 1
+    assert afmm.afmm_base_lists(q, 65537, 64, 64, 1, ent, lens, None) == 1  # above AFMM_MAX_N
