@@ -203,6 +203,24 @@ afmm_status afmm_base_lists(const float *Q, int64_t k, int64_t n_c, int64_t ldq,
                             uint32_t *d_entries, int32_t *d_lens, hipStream_t stream);
 
 /*
+ * The row-list form's lists, read back (for checking the list builder; not
+ * needed for computing products).  M: a rows x cols row-major matrix in device
+ * memory, leading dimension ld >= cols, of int32 counts (is_int = 1) or
+ * binary32 bases (is_int = 0).  With bands of `band` columns
+ * (bands = ceil(cols / band)), writes in device memory:
+ *   d_entries: [bands][rows][band] pairs of uint32 {bits of M[r][b*band + c], c}
+ *              for the entries of row r in band b that take part in an
+ *              addition (a count > 0; a base != 0, so -0.0 is dropped and NaN
+ *              kept), in ascending c; slots past the length are not written;
+ *   d_lens:    [bands][rows] int32, the number of such entries.
+ * The row-list form lists X with one band as wide as its rows (rounded up to
+ * 64) and Y with bands of 64*C columns.  Asynchronous on `stream`.
+ */
+afmm_status afmm_row_lists(int32_t is_int, const void *M, int64_t rows, int64_t cols, int64_t ld,
+                           int64_t band, uint32_t *d_entries, int32_t *d_lens,
+                           hipStream_t stream);
+
+/*
  * Synchronous data check: runs the counting pass on `stream`, waits for it,
  * and returns AFMM_ERR_NEGATIVE_INT, AFMM_ERR_INT_RANGE (split mode, an
  * entry > 256), AFMM_ERR_COUNT_OVERFLOW or AFMM_OK.

@@ -80,6 +80,7 @@ _SIGS = {
     "afmm_multiply_batched": ([ctypes.POINTER(afmm_problem), _i32, _ci, _vp], _ci),
     "afmm_split_terms": ([_ci, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _ci),
     "afmm_base_lists": ([_vp, _i64, _i64, _i64, _ci, _vp, _vp, _vp], _ci),
+    "afmm_row_lists": ([_ci, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp], _ci),
     "afmm_probe_add_rate": ([_i32, _i32, _vp, ctypes.POINTER(ctypes.c_uint64), _vp], _ci),
     "afmm_multiply_noalloc": ([_ci, _i64, _vp, _vp, _vp, _vp], _ci),
     "afmm_status_string": ([_ci], ctypes.c_char_p),

@@ -617,6 +617,22 @@ afmm_status afmm_base_lists(const float* Q, int64_t k, int64_t n_c, int64_t ldq,
     return AFMM_OK;
 }
 
+afmm_status afmm_row_lists(int32_t is_int, const void* M, int64_t rows, int64_t cols, int64_t ld,
+                           int64_t band, uint32_t* d_entries, int32_t* d_lens,
+                           hipStream_t stream) {
+    if (!M || !d_entries || !d_lens || (is_int != 0 && is_int != 1) || rows < 1 ||
+        rows > AFMM_MAX_N || cols < 1 || cols > AFMM_MAX_N || ld < cols || ld > kMaxLd ||
+        band < 1 || band > AFMM_MAX_N)
+        return AFMM_ERR_INVALID_ARG;
+    const int64_t segs = (cols + band - 1) / band * rows;
+    if (segs > ((int64_t)1 << 31)) return AFMM_ERR_INVALID_ARG;  // grid of segs / 4 blocks
+    afmm_status st = check_device();
+    if (st != AFMM_OK) return st;
+    AFMM_HIP(launch_compact_lists(is_int != 0, M, ld, (int)rows, (int)cols, (int)band,
+                                  reinterpret_cast<uint2*>(d_entries), d_lens, stream));
+    return AFMM_OK;
+}
+
 afmm_status afmm_validate(afmm_case c, int64_t n, const void* X, const void* Y, afmm_mode mode,
                           hipStream_t stream) {
     if (mode != AFMM_MODE_STRICT && mode != AFMM_MODE_SPLIT_BF16X3) return AFMM_ERR_INVALID_ARG;

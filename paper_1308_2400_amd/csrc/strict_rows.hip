@@ -97,6 +97,12 @@ hipError_t launch_compact(const void* M, int64_t ld, int rows, int cols, int ct,
     return hipGetLastError();
 }
 
+hipError_t launch_compact_lists(bool is_int, const void* M, int64_t ld, int rows, int cols,
+                                int ct, uint2* ent, int32_t* lens, hipStream_t s) {
+    return is_int ? launch_compact<true>(M, ld, rows, cols, ct, ent, lens, s, nullptr)
+                  : launch_compact<false>(M, ld, rows, cols, ct, ent, lens, s, nullptr);
+}
+
 hipError_t launch_compact_rows(int case_id, const void* X, int64_t ldx, const void* Y,
                                int64_t ldy, int m, int kd, int n, int C, const RowsLists& L,
                                hipStream_t s, const uint32_t* gate) {

@@ -24,6 +24,11 @@ RowsLists rows_lists_at(uint8_t* p, int m, int kd, int n, int C);
 hipError_t launch_compact_rows(int case_id, const void* X, int64_t ldx, const void* Y,
                                int64_t ldy, int m, int kd, int n, int C, const RowsLists& L,
                                hipStream_t s, const uint32_t* gate = nullptr);
+// One list per (band, row) of M (rows x cols, ld; bands of ct columns): the
+// entries taking part in an addition, ascending column (the pass both lists
+// above are built with).  ent [bands][rows][ct], lens [bands][rows].
+hipError_t launch_compact_lists(bool is_int, const void* M, int64_t ld, int rows, int cols,
+                                int ct, uint2* ent, int32_t* lens, hipStream_t s);
 hipError_t launch_rep_rows(int case_id, int m, int kd, int n, const RowsLists& L, float* Z,
                            int64_t ldz, int C, int W, hipStream_t s,
                            const uint32_t* gate = nullptr);

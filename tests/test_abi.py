@@ -223,3 +223,12 @@ def test_new_entry_points_reject_bad_arguments_on_host(afmm):
     assert afmm.afmm_base_lists(q, 4, 64, 64, 1, None, lens, None) == 1
     assert afmm.afmm_base_lists(q, 4, 64, 64, 1, ent, None, None) == 1
     assert afmm.afmm_base_lists(q, 65537, 64, 64, 1, ent, lens, None) == 1  # above AFMM_MAX_N
+    # the row-list read-back
+    m_ = 4096
+    assert afmm.afmm_row_lists(2, m_, 4, 64, 64, 64, ent, lens, None) == 1     # is_int not 0/1
+    assert afmm.afmm_row_lists(1, m_, 0, 64, 64, 64, ent, lens, None) == 1     # rows < 1
+    assert afmm.afmm_row_lists(1, m_, 4, 0, 64, 64, ent, lens, None) == 1      # cols < 1
+    assert afmm.afmm_row_lists(1, m_, 4, 64, 63, 64, ent, lens, None) == 1     # ld < cols
+    assert afmm.afmm_row_lists(1, m_, 4, 64, 64, 0, ent, lens, None) == 1      # band < 1
+    assert afmm.afmm_row_lists(1, None, 4, 64, 64, 64, ent, lens, None) == 1   # null pointers
+    assert afmm.afmm_row_lists(1, m_, 65536, 65536, 65536, 1, ent, lens, None) == 1  # > 2^31 lists
